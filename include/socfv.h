@@ -1,0 +1,212 @@
+/*
+ * socfv — steady state-of-charge (SOC) solve on voxelised porous electrodes, MI355X.
+ *
+ * C ABI of the GPU library libsocfv.so.  Plain pointers and sizes only.
+ *
+ * The method (Emanuel & Rycroft, "Digital Twin for Porous Electrodes in Redox Flow
+ * Batteries"): at a fixed flow field, the state of charge s obeys the transport equation
+ * of Eq. (nernst-planck-soc), whose Butler-Volmer source is affine in s at a controlled
+ * voltage (Eq. (rate-from-soc-gen)): a k0 K (s_eq - s).  The steady state is reached by the
+ * explicit pseudo-time iteration of the Algorithm "SOC at Mass Transport Limit"
+ * (s <- F s, electrode cells reset), stopped by the rule of Eq. (convergence-bv-change).
+ * Its figure of merit is the utilisation U (Eq. (utilization-def)); in the fast-kinetics
+ * limit (Eqs. (np-fast-interior), (np-fast-boundary)) with s_in = 0 and s = 1 on the
+ * electrode it is U_mt (Eq. (umt-def)).
+ *
+ * Units.  Everything is nondimensional: voxel size h = 1, diffusivity D = 1, time in
+ * h^2 / D.  Face velocities are given in units of D / h (a face Peclet number).  The
+ * reaction enters as Da = k0 K h / D per fibre face of a surface cell, with
+ * K = e^{alpha V} + e^{(alpha-1) V} the slope of the affine rate.
+ *
+ * Layout.  Grids are (nz, ny, nx), x fastest, cell index x + nx*(y + ny*z); flow enters
+ * through the x = 0 plane and leaves through x = nx.  Staggered face velocities, positive
+ * along +axis: ux (nz, ny, nx+1), uy (nz, ny+1, nx), uz (nz+1, ny, nx), FP64.
+ *
+ * Discretisation (finite volumes, one definition shared by every entry point):
+ *   R_P(s) = sum_f [ -max(w_f,0) s_P - min(w_f,0) s_up(f) + G_f (s_nb(f) - s_P) ]
+ *            + lam_P (s_eq - s_P),          lam_P = Da * kappa_P * n_f(P)
+ * w_f = outward normal velocity of face f; interior faces (pore on both sides): upwind
+ * value of the neighbour, G = 1; inlet faces: upwind value s_in, G = 2 (Dirichlet value
+ * on the face); outlet faces: upwind value s_P, G = 0 (no concentration gradient); faces
+ * shared with a fibre voxel and the y / z walls carry no flux and must have w = 0.
+ * n_f(P) = number of faces P shares with fibre voxels (its specific area a = n_f / h).
+ * Iteration: s <- s + dt R(s), dt = cfl / max_P (sum_f max(w_f,0) + sum_f G_f + lam_P).
+ * Residual: res = tau * sqrt(mean over pore cells of R_P^2) = (tau/dt)||s^{n+1}-s^n||_rms
+ * with tau = nx*ny*nz / Q (nominal volume over inlet flow).
+ *
+ * Ownership.  Every pointer argument is owned by the caller.  Device pointers
+ * (marked "device") must stay valid for the duration of the call only: the library
+ * copies what it keeps into buffers it owns, freed by socfv_destroy.  All device work is
+ * enqueued on the caller's HIP stream (NULL = default stream); calls return when their
+ * outputs are complete.
+ *
+ * Errors.  Every int-returning call returns a socfv_status.  No exception crosses the
+ * ABI; socfv_last_error() gives a message for the calling thread's last failure.
+ * A context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef SOCFV_H
+#define SOCFV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SOCFV_OK = 0,
+  SOCFV_NOT_CONVERGED = 1,   /* max_iter reached; outputs are still written */
+  SOCFV_INVALID_ARG = -1,
+  SOCFV_BAD_GEOMETRY = -2,   /* pore cell not face-connected to the inlet, no inlet/outlet pore */
+  SOCFV_BAD_VELOCITY = -3,   /* non-finite, flux through a closed face, inlet backflow, Q <= 0,
+                                or divergence above the tolerance */
+  SOCFV_DIVERGED = -4,       /* non-finite residual or s outside [min(s_in,s_eq), max(..)] */
+  SOCFV_HIP_ERROR = -5,
+  SOCFV_OOM = -6
+} socfv_status;
+
+enum { SOCFV_FINITE_RATE = 0, SOCFV_PINNED = 1 };
+enum {
+  SOCFV_FP64 = 0,            /* every sweep in FP64 */
+  SOCFV_FP32 = 1,            /* FP32 sweeps on a correction against an FP64 residual,
+                                FP64 reductions, FP64 refresh and polish */
+  SOCFV_FP32_PLAIN = 2       /* FP32 sweeps on s itself until FP32 stagnates (diagnostic) */
+};
+
+typedef struct socfv_ctx socfv_ctx;
+
+typedef struct {
+  double s_in;        /* inlet Dirichlet value */
+  double s_eq;        /* equilibrium SOC of the electrode (sigma(V)) */
+  double Da;          /* reaction number per fibre face, k0 K h / D (FINITE_RATE) */
+  int mode;           /* SOCFV_FINITE_RATE or SOCFV_PINNED (electrode cells held at s_eq) */
+  int precision;      /* SOCFV_FP64, SOCFV_FP32 or SOCFV_FP32_PLAIN */
+  double cfl;         /* dt = cfl / max diag; 0 < cfl <= 1 keeps the iteration monotone */
+  double tol;         /* stop when res < tol */
+  long max_iter;      /* cap on explicit sweeps (all precisions) */
+  int check_every;    /* sweeps between residual checks (>= 2, even; rounded up to even) */
+  int polish_iters;   /* FP32 mode: FP64 sweeps after the last refresh (0 = check_every) */
+} socfv_params;
+
+typedef struct {
+  long iterations;    /* explicit sweeps done in total */
+  long it_fp32;       /* FP32 sweeps */
+  long it_fp64;       /* FP64 sweeps (FP64 mode, refreshes and polish) */
+  int cycles;         /* FP32 mode: FP64 residual refreshes */
+  int status;         /* socfv_status of the solve */
+  double residual;    /* final residual tau * rms(R) (FP64 in FP64 / FP32 modes) */
+  double dt, tau;     /* pseudo-time step and flow-through time */
+  double U;           /* (sbar_out - s_in) / (s_eq - s_in) */
+  double s_out;       /* outlet flux-weighted mean SOC, sum_out w s / sum_out w */
+  double flux_in;     /* advective + diffusive inlet flux of s */
+  double flux_in_adv; /* advective inlet flux only, sum_in u s_in */
+  double flux_out;    /* sum_out w s */
+  double reaction;    /* sum lam (s - s_eq) (finite rate) or what held cells absorb (pinned) */
+  double sum_R;       /* sum of R over updated cells: flux_in - flux_out - reaction */
+  double q_out;       /* outlet flow, sum_out w */
+  double seconds;     /* wall time of the call */
+  double max_abs_s_change_fp32; /* FP32_PLAIN: last max |dt R| seen (stagnation diagnostic) */
+} socfv_stats;
+
+/* Fill p with defaults: s_in 1, s_eq 0, Da 0.45, FINITE_RATE, FP32, cfl 0.4, tol 1e-8,
+ * max_iter 10^8, check_every 200, polish_iters 0. */
+void socfv_default_params(socfv_params *p);
+
+/*
+ * Geometry (pore / fibre voxels, the electrode's implicit-function description reduced to
+ * voxels).  solid: device, uint8 (nz, ny, nx), nonzero = fibre voxel.  Builds the per-cell
+ * flags (which faces touch fibre, pore bit) on the GPU and checks on the host that every
+ * pore cell is face-connected to a pore cell of the inlet plane and that the outlet plane
+ * has a pore cell (BAD_GEOMETRY otherwise).  *out receives a new context.
+ */
+int socfv_setup_geometry(socfv_ctx **out, int nx, int ny, int nz, const uint8_t *solid,
+                         void *hip_stream);
+
+/*
+ * Face velocities (device, FP64, staggered layout above), multiplied by q (the flow is
+ * linear in the driving pressure in the Stokes regime, so one field serves every flow
+ * rate).  Stored in FP32 and FP64.  Rejects (BAD_VELOCITY) non-finite values, non-zero
+ * velocity on a face shared with a fibre voxel or on a y/z wall, backflow through the
+ * inlet, no inflow, and a cell divergence above 1e-6 times the largest face velocity.
+ */
+int socfv_set_velocity(socfv_ctx *c, const double *ux, const double *uy, const double *uz,
+                       double q, void *hip_stream);
+
+/* Per-voxel reaction activity kappa (device, FP32 (nz, ny, nx); NULL = 1 everywhere).
+ * lam_P = Da * kappa_P * n_f(P). */
+int socfv_set_activity(socfv_ctx *c, const float *kappa, void *hip_stream);
+
+/*
+ * Steady state by the explicit iteration.  s_init (device FP64 (nz,ny,nx), nullable):
+ * start state (default s_in on pore cells); held cells always start at s_eq.
+ * s_out (device FP64 (nz,ny,nx), nullable): steady state (fibre cells 0).  The state is
+ * also kept in the context for socfv_solve_soc_adjoint.  st (host, nullable): stats,
+ * including U and the flux balance of the final state.
+ * Returns OK, NOT_CONVERGED (max_iter reached), DIVERGED or an error.
+ */
+int socfv_solve_soc_steady(socfv_ctx *c, const socfv_params *p, const double *s_init,
+                           double *s_out, socfv_stats *st, void *hip_stream);
+
+/*
+ * Mass-transport-limited utilisation U_mt: the PINNED solve with s_in = 0, s_eq = 1
+ * (p's mode, s_in, s_eq and Da are ignored; its precision, cfl, tol, max_iter,
+ * check_every are used; p may be NULL for defaults).  *U_mt (host) receives the result;
+ * s_out / st as in socfv_solve_soc_steady.
+ */
+int socfv_compute_umt(socfv_ctx *c, const socfv_params *p, double *U_mt, double *s_out,
+                      socfv_stats *st, void *hip_stream);
+
+/*
+ * U and the flux balance of a given state s (device FP64 (nz,ny,nx); NULL = the state
+ * of the last solve) under p's s_in / s_eq / Da / mode.  Writes the output fields of st
+ * (U ... q_out) and st->residual (FP64 residual of that state).
+ */
+int socfv_evaluate(socfv_ctx *c, const socfv_params *p, const double *s, socfv_stats *st,
+                   void *hip_stream);
+
+/*
+ * Discrete adjoint of U at the last steady state of this context (which must come from
+ * socfv_solve_soc_steady with the same p): solves A^T psi = dU/ds by the same explicit
+ * iteration with reversed advection (psi <- psi + dt (g - A^T psi)), to
+ * ||g - A^T psi|| / ||g|| < p->tol_adjoint... (p->tol is used), then
+ *   dU_dkappa[P] = Da n_f(P) psi_P (s_eq - s_P)   (device FP64 (nz,ny,nx), nullable;
+ *                                                 FINITE_RATE only, 0 elsewhere)
+ *   *dU_dlnq     = sum_P psi_P Radv_P(s)          (host; derivative in ln q, u = q u0:
+ *                                                 divide by q for dU/dq)
+ * psi_out (device FP64, nullable) receives psi.  Held cells (PINNED) get psi = 0.
+ */
+int socfv_solve_soc_adjoint(socfv_ctx *c, const socfv_params *p, double *dU_dkappa,
+                            double *dU_dlnq, double *psi_out, socfv_stats *st,
+                            void *hip_stream);
+
+/*
+ * Many problems (contexts with geometry and velocity set) solved together: every
+ * FP32 / FP64 sweep is one launch over a tile work list spanning all unfinished problems,
+ * and chunks of sweeps are captured once as a hipGraph and replayed.  Each problem
+ * stops at its own residual (its own p[i]) and keeps its own dt and tau.  p and st are
+ * host arrays of n entries; s_out (host array of n device pointers, nullable entries).
+ */
+int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
+                      double *const *s_out, socfv_stats *st, void *hip_stream);
+
+/*
+ * Tile shapes.  The stencil sweeps work on (tile_x x tile_y) columns of cells marching
+ * z_chunk cells along z.  socfv_set_tiles overrides them for a context (0 = keep);
+ * socfv_autotune times the candidate shapes on this context's problem (FP32 sweeps,
+ * `sweeps` each) and keeps the fastest; best[3] (host, nullable) receives it.
+ */
+int socfv_set_tiles(socfv_ctx *c, int tile_y, int z_chunk);
+int socfv_autotune(socfv_ctx *c, int sweeps, int best[3], void *hip_stream);
+
+/* Problem facts: dims[3] = nx, ny, nz; counts[3] = pore cells, reactive cells,
+ * cells not connected (always 0 after a successful setup). */
+int socfv_info(const socfv_ctx *c, int dims[3], long counts[3]);
+
+void socfv_destroy(socfv_ctx *c);
+const char *socfv_last_error(void);
+int socfv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SOCFV_H */

@@ -1,0 +1,862 @@
+// Host runtime of libsocfv: contexts, validation, the convergence loop, mixed precision,
+// outputs, adjoint.  Implements the C ABI declared in include/socfv.h.
+#include "../../include/socfv.h"
+#include "internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+using namespace socfv;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(e_ == hipErrorOutOfMemory ? SOCFV_OOM : SOCFV_HIP_ERROR, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                      \
+  } while (0)
+
+#define TRY(expr)            \
+  do {                       \
+    int r_ = (expr);         \
+    if (r_ < 0) return r_;   \
+  } while (0)
+
+void hfree(void *ptr) {
+  if (ptr) (void)hipFree(ptr);
+}
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct socfv_ctx {
+  Grid g{};
+  hipStream_t st = nullptr;      // library stream (default priority)
+  hipEvent_t ev = nullptr;
+  uint8_t *flags = nullptr;
+  float *w32[4] = {nullptr, nullptr, nullptr, nullptr};
+  double *w64[4] = {nullptr, nullptr, nullptr, nullptr};
+  float *kappa = nullptr;
+  float *s32[2] = {nullptr, nullptr};
+  double *s64[2] = {nullptr, nullptr};
+  float *r0 = nullptr;
+  double *aux64 = nullptr;       // adjoint psi (FP64) ping-pong partner etc.
+  double *aux64b = nullptr;
+  double *partial = nullptr;
+  long long partial_cap = 0;     // doubles
+  double *dres = nullptr;        // device result slots
+  double *hres = nullptr;        // pinned host mirror
+  long npore = 0, nreact = 0, ninlet = 0, noutlet = 0;
+  bool have_velocity = false;
+  double Q_in = 0, div_max = 0, u_max = 0;
+  Tiles tiles{4, 8};
+  bool tiles_fixed = false;
+  // last forward solution
+  bool have_state = false;
+  int state_buf = 0;             // s64[state_buf] holds the last steady state
+  socfv_params last_p{};
+};
+
+namespace {
+
+Faces<float> faces32(const socfv_ctx *c) { return {c->w32[0], c->w32[1], c->w32[2], c->w32[3]}; }
+Faces<double> faces64(const socfv_ctx *c) { return {c->w64[0], c->w64[1], c->w64[2], c->w64[3]}; }
+
+Tiles auto_tiles(const Grid &g, int ty) {
+  long long txy = (long long)((g.nx + 63) / 64) * ((g.ny + ty - 1) / ty);
+  long long zc = (long long)g.nz * txy / 8192;
+  if (zc < 1) zc = 1;
+  if (zc > 32) zc = 32;
+  if (zc > g.nz) zc = g.nz;
+  return Tiles{ty, (int)zc};
+}
+
+long long sweep_blocks(const Grid &g, const Tiles &t) {
+  dim3 d = sweep_grid(g, t);
+  return (long long)d.x * d.y * d.z;
+}
+
+int ensure_partial(socfv_ctx *c, long long doubles) {
+  if (doubles <= c->partial_cap) return 0;
+  if (c->partial) hfree(c->partial);
+  c->partial = nullptr;
+  c->partial_cap = 0;
+  HIPCHK(hipMalloc(&c->partial, sizeof(double) * doubles));
+  c->partial_cap = doubles;
+  return 0;
+}
+
+// reduce nblk x nv partials into host values out[0..nv-1]
+int reduce_to_host(socfv_ctx *c, int nblk, int nv, unsigned maxmask, double *out) {
+  launch_reduce(c->partial, nblk, nv, maxmask, c->dres, c->st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->hres, c->dres, sizeof(double) * nv, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  for (int k = 0; k < nv; ++k) out[k] = c->hres[k];
+  return 0;
+}
+
+// join the caller's stream: library work starts after the caller's prior work
+int enter(socfv_ctx *c, void *user_stream) {
+  HIPCHK(hipEventRecord(c->ev, (hipStream_t)user_stream));
+  HIPCHK(hipStreamWaitEvent(c->st, c->ev, 0));
+  return 0;
+}
+
+// outputs complete before returning; the caller's stream waits on the library's
+int leave(socfv_ctx *c, void *user_stream) {
+  HIPCHK(hipEventRecord(c->ev, c->st));
+  HIPCHK(hipStreamWaitEvent((hipStream_t)user_stream, c->ev, 0));
+  HIPCHK(hipStreamSynchronize(c->st));
+  return 0;
+}
+
+int ensure_state(socfv_ctx *c) {
+  const size_t n = (size_t)c->g.n;
+  for (int k = 0; k < 2; ++k) {
+    if (!c->s64[k]) HIPCHK(hipMalloc(&c->s64[k], sizeof(double) * n));
+    if (!c->s32[k]) HIPCHK(hipMalloc(&c->s32[k], sizeof(float) * n));
+  }
+  if (!c->r0) HIPCHK(hipMalloc(&c->r0, sizeof(float) * n));
+  return ensure_partial(c, (long long)NV * sweep_blocks(c->g, c->tiles) + 64);
+}
+
+int ensure_adjoint(socfv_ctx *c) {
+  const size_t n = (size_t)c->g.n;
+  if (!c->aux64) HIPCHK(hipMalloc(&c->aux64, sizeof(double) * n));
+  if (!c->aux64b) HIPCHK(hipMalloc(&c->aux64b, sizeof(double) * n));
+  return 0;
+}
+
+int check_params(const socfv_params *p) {
+  if (!p) return fail(SOCFV_INVALID_ARG, "params is NULL");
+  if (!(p->cfl > 0.0 && p->cfl <= 1.0)) return fail(SOCFV_INVALID_ARG, "cfl must be in (0, 1]");
+  if (!(p->tol >= 0.0)) return fail(SOCFV_INVALID_ARG, "tol must be >= 0");
+  if (p->max_iter < 1) return fail(SOCFV_INVALID_ARG, "max_iter must be >= 1");
+  if (p->check_every < 1) return fail(SOCFV_INVALID_ARG, "check_every must be >= 1");
+  if (p->mode != SOCFV_FINITE_RATE && p->mode != SOCFV_PINNED)
+    return fail(SOCFV_INVALID_ARG, "unknown mode %d", p->mode);
+  if (p->precision < SOCFV_FP64 || p->precision > SOCFV_FP32_PLAIN)
+    return fail(SOCFV_INVALID_ARG, "unknown precision %d", p->precision);
+  if (!std::isfinite(p->s_in) || !std::isfinite(p->s_eq) || !std::isfinite(p->Da) || p->Da < 0)
+    return fail(SOCFV_INVALID_ARG, "s_in, s_eq must be finite and Da >= 0");
+  if (p->s_in == p->s_eq) return fail(SOCFV_INVALID_ARG, "s_in must differ from s_eq (U undefined)");
+  return 0;
+}
+
+struct Solver {
+  socfv_ctx *c;
+  const socfv_params *p;
+  int pinned;
+  double dt = 0, tau = 0;
+  double lo = 0, hi = 0;
+  long it = 0, it32 = 0, it64 = 0;
+  int cycles = 0;
+  Tiles t;
+  long long nblk = 0;
+
+  int setup() {
+    pinned = p->mode == SOCFV_PINNED;
+    t = c->tiles;
+    nblk = sweep_blocks(c->g, t);
+    TRY(ensure_state(c));
+    // time step: cfl over the largest diagonal of the updated cells
+    const int mb = flags_blocks(c->g);
+    TRY(ensure_partial(c, (long long)mb * NV2 + 64));
+    launch_maxdiag(c->g, c->flags, faces64(c), c->kappa, p->Da, pinned, c->partial, mb, c->st);
+    HIPCHK(hipGetLastError());
+    double md = 0;
+    TRY(reduce_to_host(c, mb, 1, 1u, &md));
+    if (!(md > 0)) return fail(SOCFV_BAD_VELOCITY, "no updated cell (max diagonal %g)", md);
+    dt = p->cfl / md;
+    tau = (double)c->g.n / c->Q_in;
+    lo = std::fmin(p->s_in, p->s_eq) - 1e-6;
+    hi = std::fmax(p->s_in, p->s_eq) + 1e-6;
+    return 0;
+  }
+
+  double res_of(double ss) const { return tau * std::sqrt(ss / (double)c->npore); }
+
+  template <typename T>
+  SweepArgs<T> sweep_args(const T *s, T *s_new, bool dc, double *partial) {
+    SweepArgs<T> a;
+    a.g = c->g;
+    a.flags = c->flags;
+    a.kappa = c->kappa;
+    a.s = s;
+    a.s_new = s_new;
+    a.r0 = dc ? c->r0 : nullptr;
+    a.dt = (T)dt;
+    a.s_in = dc ? T(0) : (T)p->s_in;
+    a.s_eq = dc ? T(0) : (T)p->s_eq;
+    a.Da = (T)p->Da;
+    a.pinned = pinned;
+    a.lo = lo;
+    a.hi = hi;
+    a.partial = partial;
+    a.zc = t.zc;
+    return a;
+  }
+
+  // k sweeps ping-ponging buf[cur] -> buf[cur^1]; partials from the last one.
+  template <typename T>
+  int chunk(T *buf0, T *buf1, int &cur, int k, bool dc, Faces<T> w, double out[NV]) {
+    T *buf[2] = {buf0, buf1};
+    for (int j = 0; j < k; ++j) {
+      SweepArgs<T> a = sweep_args<T>(buf[cur], buf[cur ^ 1], dc, j == k - 1 ? c->partial : nullptr);
+      a.w = w;
+      launch_sweep<T>(a, t, c->st);
+      cur ^= 1;
+    }
+    HIPCHK(hipGetLastError());
+    return reduce_to_host(c, (int)nblk, NV, 0u, out);
+  }
+
+  // FP64 refresh: s64[dst] = s64[src] + delta; r0 = R64; returns res and violations
+  int refresh(int src, int dst, const float *delta, double out[NV]) {
+    RefreshArgs a;
+    a.g = c->g;
+    a.flags = c->flags;
+    a.w = faces64(c);
+    a.kappa = c->kappa;
+    a.s64 = c->s64[src];
+    a.delta = delta;
+    a.s64_new = c->s64[dst];
+    a.r0 = c->r0;
+    a.s_in = p->s_in;
+    a.s_eq = p->s_eq;
+    a.Da = p->Da;
+    a.pinned = pinned;
+    a.lo = lo;
+    a.hi = hi;
+    a.partial = c->partial;
+    a.zc = t.zc;
+    launch_refresh(a, t, c->st);
+    HIPCHK(hipGetLastError());
+    ++it64;
+    return reduce_to_host(c, (int)nblk, NV, 0u, out);
+  }
+
+  int check(const double out[NV], double res) {
+    if (!std::isfinite(res) || out[1] > 0.0)
+      return fail(SOCFV_DIVERGED, "iteration diverged at sweep %ld (residual %g, %g cells out of "
+                  "bounds or non-finite)", it, res, out[1]);
+    return 0;
+  }
+
+  int chunk_len() const {
+    int k = p->check_every < 2 ? 2 : p->check_every;
+    return k + (k & 1);
+  }
+
+  // FP64 sweeps from s64[cur] until res < tol or max_iter.  Returns status.
+  int run_fp64(int &cur, double &res, long budget) {
+    const int K = chunk_len();
+    double out[NV];
+    int status = SOCFV_NOT_CONVERGED;
+    long done = 0;
+    while (done < budget) {
+      long k = std::min<long>(K, budget - done);
+      TRY(chunk<double>(c->s64[0], c->s64[1], cur, (int)k, false, faces64(c), out));
+      done += k;
+      it += k;
+      it64 += k;
+      res = res_of(out[0]);
+      TRY(check(out, res));
+      if (res < p->tol) { status = SOCFV_OK; break; }
+    }
+    return status;
+  }
+
+  int solve(const double *s_init, double *res_final, int *state_buf) {
+    TRY(setup());
+    const long long n = c->g.n;
+    launch_init_state(c->g, c->flags, s_init, p->s_in, p->s_eq, pinned, c->s64[0], c->st);
+    HIPCHK(hipGetLastError());
+    double out[NV];
+    double res = INFINITY;
+    int status = SOCFV_NOT_CONVERGED;
+    int cur = 0;
+    if (p->precision == SOCFV_FP64) {
+      launch_fill_f64(c->s64[1], n, 0.0, c->st);
+      status = run_fp64(cur, res, p->max_iter);
+    } else if (p->precision == SOCFV_FP32_PLAIN) {
+      launch_f64_to_f32(c->s64[0], c->s32[0], n, c->st);
+      launch_fill_f32(c->s32[1], n, 0.0f, c->st);
+      const int K = chunk_len();
+      double best = INFINITY;
+      int stall = 0;
+      int c32 = 0;
+      while (it < p->max_iter) {
+        long k = std::min<long>(K, p->max_iter - it);
+        TRY(chunk<float>(c->s32[0], c->s32[1], c32, (int)k, false, faces32(c), out));
+        it += k;
+        it32 += k;
+        res = res_of(out[0]);
+        TRY(check(out, res));
+        if (res < p->tol) { status = SOCFV_OK; break; }
+        if (res < 0.999 * best) { best = res; stall = 0; }
+        else if (++stall >= 8) break;            // FP32 stagnation
+      }
+      launch_f32_to_f64(c->s32[c32], c->s64[0], n, c->st);
+      cur = 0;
+    } else {
+      // FP32 sweeps on a correction delta against the FP64 residual r0 of s64:
+      //   delta <- delta + dt (r0 - A delta); s64 += delta; r0 = b - A s64 (FP64 refresh)
+      TRY(refresh(0, 1, nullptr, out));
+      cur = 1;
+      res = res_of(out[0]);
+      TRY(check(out, res));
+      const int K = chunk_len();
+      while (res >= p->tol && it < p->max_iter) {
+        launch_fill_f32(c->s32[0], n, 0.0f, c->st);
+        launch_fill_f32(c->s32[1], n, 0.0f, c->st);
+        int cd = 0;
+        const double target = std::fmax(0.5 * p->tol, 1e-4 * res);
+        double best = INFINITY;
+        int stall = 0;
+        while (it < p->max_iter) {
+          long k = std::min<long>(K, p->max_iter - it);
+          TRY(chunk<float>(c->s32[0], c->s32[1], cd, (int)k, true, faces32(c), out));
+          it += k;
+          it32 += k;
+          const double ri = res_of(out[0]);
+          if (!std::isfinite(ri) || out[1] > 0)
+            return fail(SOCFV_DIVERGED, "correction sweeps diverged at sweep %ld", it);
+          if (ri < target) break;
+          if (ri < 0.999 * best) { best = ri; stall = 0; }
+          else if (++stall >= 8) break;
+        }
+        TRY(refresh(cur, cur ^ 1, c->s32[cd], out));
+        cur ^= 1;
+        ++cycles;
+        res = res_of(out[0]);
+        TRY(check(out, res));
+      }
+      if (res < p->tol) status = SOCFV_OK;
+      // FP64 polish sweeps from the refreshed state
+      long np = p->polish_iters > 0 ? p->polish_iters : chunk_len();
+      np += np & 1;
+      if (status == SOCFV_OK || it < p->max_iter) {
+        int pc = cur;
+        double *b0 = c->s64[0], *b1 = c->s64[1];
+        (void)b0; (void)b1;
+        double pres = res;
+        long save = it;
+        int st2 = run_fp64(pc, pres, np);
+        (void)st2;
+        (void)save;
+        cur = pc;
+        res = pres;
+        status = res < p->tol ? SOCFV_OK : SOCFV_NOT_CONVERGED;
+      }
+    }
+    *res_final = res;
+    *state_buf = cur;
+    return status;
+  }
+};
+
+int eval_outputs(socfv_ctx *c, const socfv_params *p, const double *s, socfv_stats *st) {
+  const int nb = outputs_blocks(c->g);
+  TRY(ensure_partial(c, (long long)nb * NV2 + 64));
+  launch_outputs(c->g, c->flags, faces64(c), c->kappa, s, p->s_in, p->s_eq, p->Da,
+                 p->mode == SOCFV_PINNED, c->partial, nb, c->st);
+  HIPCHK(hipGetLastError());
+  double o[NV2];
+  TRY(reduce_to_host(c, nb, NV2, 0u, o));
+  st->s_out = o[0] / o[1];
+  st->q_out = o[1];
+  st->flux_out = o[0];
+  st->flux_in = o[2];
+  st->flux_in_adv = o[3];
+  st->reaction = o[4];
+  st->sum_R = o[5];
+  st->U = (st->s_out - p->s_in) / (p->s_eq - p->s_in);
+  const double tau = (double)c->g.n / c->Q_in;
+  st->tau = tau;
+  st->residual = tau * std::sqrt(o[6] / (double)c->npore);
+  return 0;
+}
+
+}  // namespace
+
+// ======================================================================================
+// C ABI
+// ======================================================================================
+
+extern "C" {
+
+int socfv_version(void) { return 1; }
+
+const char *socfv_last_error(void) { return g_err.c_str(); }
+
+void socfv_default_params(socfv_params *p) {
+  if (!p) return;
+  p->s_in = 1.0;
+  p->s_eq = 0.0;
+  p->Da = 0.45;
+  p->mode = SOCFV_FINITE_RATE;
+  p->precision = SOCFV_FP32;
+  p->cfl = 0.4;
+  p->tol = 1e-8;
+  p->max_iter = 100000000L;
+  p->check_every = 200;
+  p->polish_iters = 0;
+}
+
+void socfv_destroy(socfv_ctx *c) {
+  if (!c) return;
+  if (c->st) (void)hipStreamSynchronize(c->st);
+  hfree(c->flags);
+  for (int k = 0; k < 4; ++k) { hfree(c->w32[k]); hfree(c->w64[k]); }
+  hfree(c->kappa);
+  for (int k = 0; k < 2; ++k) { hfree(c->s32[k]); hfree(c->s64[k]); }
+  hfree(c->r0);
+  hfree(c->aux64);
+  hfree(c->aux64b);
+  hfree(c->partial);
+  hfree(c->dres);
+  if (c->hres) (void)hipHostFree(c->hres);
+  if (c->ev) (void)hipEventDestroy(c->ev);
+  if (c->st) (void)hipStreamDestroy(c->st);
+  delete c;
+}
+
+int socfv_setup_geometry(socfv_ctx **out, int nx, int ny, int nz, const uint8_t *solid,
+                         void *hip_stream) {
+  if (!out) return fail(SOCFV_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (nx < 1 || ny < 1 || nz < 1) return fail(SOCFV_INVALID_ARG, "bad dims %d %d %d", nx, ny, nz);
+  if (!solid) return fail(SOCFV_INVALID_ARG, "solid is NULL");
+  const long long n = (long long)nx * ny * nz;
+  if (n > (1ll << 40)) return fail(SOCFV_INVALID_ARG, "grid too large");
+  socfv_ctx *c = new socfv_ctx();
+  c->g = Grid{nx, ny, nz, n};
+  c->tiles = auto_tiles(c->g, 4);
+  auto bail = [&](int code) { socfv_destroy(c); return code; };
+  if (hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess)
+    return bail(fail(SOCFV_HIP_ERROR, "stream/event creation failed"));
+  if (hipMalloc(&c->flags, (size_t)n) != hipSuccess ||
+      hipMalloc(&c->dres, sizeof(double) * 64) != hipSuccess ||
+      hipHostMalloc(&c->hres, sizeof(double) * 64, hipHostMallocDefault) != hipSuccess)
+    return bail(fail(SOCFV_OOM, "device allocation failed (%lld cells)", n));
+  int r = enter(c, hip_stream);
+  if (r < 0) return bail(r);
+  const int nb = flags_blocks(c->g);
+  if ((r = ensure_partial(c, 4ll * nb + 64)) < 0) return bail(r);
+  launch_flags(c->g, solid, c->flags, c->partial, nb, c->st);
+  if (hipGetLastError() != hipSuccess) return bail(fail(SOCFV_HIP_ERROR, "flags kernel launch"));
+  double cnt[4];
+  if ((r = reduce_to_host(c, nb, 4, 0u, cnt)) < 0) return bail(r);
+  c->npore = (long)cnt[0];
+  c->nreact = (long)cnt[1];
+  c->ninlet = (long)cnt[2];
+  c->noutlet = (long)cnt[3];
+  if (c->ninlet == 0 || c->noutlet == 0)
+    return bail(fail(SOCFV_BAD_GEOMETRY, "no pore cell in the %s plane",
+                     c->ninlet == 0 ? "inlet" : "outlet"));
+  // every pore cell must be face-connected to the inlet plane (host breadth-first search)
+  std::vector<uint8_t> fl((size_t)n);
+  if (hipMemcpyAsync(fl.data(), c->flags, (size_t)n, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+      hipStreamSynchronize(c->st) != hipSuccess)
+    return bail(fail(SOCFV_HIP_ERROR, "flags copy"));
+  std::vector<uint8_t> seen((size_t)n, 0);
+  std::vector<long long> queue;
+  queue.reserve((size_t)c->npore);
+  const long long pl = (long long)nx * ny;
+  for (long long z = 0; z < nz; ++z)
+    for (long long y = 0; y < ny; ++y) {
+      long long i = nx * (y + ny * z);
+      if (fl[i] & FL_PORE) { seen[i] = 1; queue.push_back(i); }
+    }
+  for (size_t h = 0; h < queue.size(); ++h) {
+    const long long i = queue[h];
+    const long long x = i % nx, y = (i / nx) % ny, z = i / pl;
+    const long long nb6[6] = {x > 0 ? i - 1 : -1, x < nx - 1 ? i + 1 : -1,
+                              y > 0 ? i - nx : -1, y < ny - 1 ? i + nx : -1,
+                              z > 0 ? i - pl : -1, z < nz - 1 ? i + pl : -1};
+    for (long long j : nb6)
+      if (j >= 0 && !seen[j] && (fl[j] & FL_PORE)) { seen[j] = 1; queue.push_back(j); }
+  }
+  const long long missing = c->npore - (long long)queue.size();
+  if (missing != 0)
+    return bail(fail(SOCFV_BAD_GEOMETRY, "%lld pore cells are not face-connected to the inlet",
+                     missing));
+  if ((r = leave(c, hip_stream)) < 0) return bail(r);
+  *out = c;
+  return SOCFV_OK;
+}
+
+int socfv_set_velocity(socfv_ctx *c, const double *ux, const double *uy, const double *uz,
+                       double q, void *hip_stream) {
+  if (!c || !ux || !uy || !uz) return fail(SOCFV_INVALID_ARG, "NULL argument");
+  if (!std::isfinite(q) || q <= 0) return fail(SOCFV_INVALID_ARG, "q must be finite and > 0");
+  const size_t n = (size_t)c->g.n, plane = (size_t)c->g.ny * c->g.nz;
+  for (int k = 0; k < 3; ++k) {
+    if (!c->w32[k]) HIPCHK(hipMalloc(&c->w32[k], sizeof(float) * n));
+    if (!c->w64[k]) HIPCHK(hipMalloc(&c->w64[k], sizeof(double) * n));
+  }
+  if (!c->w32[3]) HIPCHK(hipMalloc(&c->w32[3], sizeof(float) * plane));
+  if (!c->w64[3]) HIPCHK(hipMalloc(&c->w64[3], sizeof(double) * plane));
+  TRY(enter(c, hip_stream));
+  const int nb = velocity_blocks(c->g);
+  TRY(ensure_partial(c, 4ll * nb + 64));
+  launch_velocity(c->g, c->flags, ux, uy, uz, q, c->w32, c->w64, c->partial, nb, c->st);
+  HIPCHK(hipGetLastError());
+  double v[4];
+  TRY(reduce_to_host(c, nb, 4, 0x6u, v));
+  c->have_velocity = false;
+  c->have_state = false;
+  if (v[3] > 0)
+    return fail(SOCFV_BAD_VELOCITY, "%.0f faces: non-finite, flux through a closed face or inlet "
+                "backflow", v[3]);
+  if (!(v[0] > 0)) return fail(SOCFV_BAD_VELOCITY, "no inflow (Q = %g)", v[0]);
+  if (v[1] > 1e-6 * v[2])
+    return fail(SOCFV_BAD_VELOCITY, "cell divergence %g exceeds 1e-6 x max velocity %g", v[1], v[2]);
+  c->Q_in = v[0];
+  c->div_max = v[1];
+  c->u_max = v[2];
+  c->have_velocity = true;
+  TRY(leave(c, hip_stream));
+  return SOCFV_OK;
+}
+
+int socfv_set_activity(socfv_ctx *c, const float *kappa, void *hip_stream) {
+  if (!c) return fail(SOCFV_INVALID_ARG, "NULL context");
+  c->have_state = false;
+  if (!kappa) {
+    if (c->kappa) hfree(c->kappa);
+    c->kappa = nullptr;
+    return SOCFV_OK;
+  }
+  if (!c->kappa) HIPCHK(hipMalloc(&c->kappa, sizeof(float) * (size_t)c->g.n));
+  TRY(enter(c, hip_stream));
+  HIPCHK(hipMemcpyAsync(c->kappa, kappa, sizeof(float) * (size_t)c->g.n, hipMemcpyDeviceToDevice,
+                        c->st));
+  TRY(leave(c, hip_stream));
+  return SOCFV_OK;
+}
+
+int socfv_solve_soc_steady(socfv_ctx *c, const socfv_params *p, const double *s_init,
+                           double *s_out, socfv_stats *st, void *hip_stream) {
+  const double t0 = now_s();
+  if (!c) return fail(SOCFV_INVALID_ARG, "NULL context");
+  TRY(check_params(p));
+  if (!c->have_velocity) return fail(SOCFV_INVALID_ARG, "velocity not set");
+  TRY(enter(c, hip_stream));
+  Solver S{c, p};
+  double res = 0;
+  int buf = 0;
+  c->have_state = false;
+  int status = S.solve(s_init, &res, &buf);
+  if (status < 0) {
+    (void)hipStreamSynchronize(c->st);
+    return status;
+  }
+  c->have_state = true;
+  c->state_buf = buf;
+  c->last_p = *p;
+  socfv_stats s{};
+  TRY(eval_outputs(c, p, c->s64[buf], &s));
+  if (s_out)
+    HIPCHK(hipMemcpyAsync(s_out, c->s64[buf], sizeof(double) * (size_t)c->g.n,
+                          hipMemcpyDeviceToDevice, c->st));
+  TRY(leave(c, hip_stream));
+  s.iterations = S.it;
+  s.it_fp32 = S.it32;
+  s.it_fp64 = S.it64;
+  s.cycles = S.cycles;
+  s.status = status;
+  s.dt = S.dt;
+  s.tau = S.tau;
+  s.residual = p->precision == SOCFV_FP64 ? res : s.residual;
+  s.seconds = now_s() - t0;
+  if (st) *st = s;
+  if (status == SOCFV_NOT_CONVERGED)
+    fail(SOCFV_NOT_CONVERGED, "not converged after %ld sweeps (residual %g)", S.it, res);
+  return status;
+}
+
+int socfv_compute_umt(socfv_ctx *c, const socfv_params *p, double *U_mt, double *s_out,
+                      socfv_stats *st, void *hip_stream) {
+  socfv_params q;
+  if (p) q = *p; else socfv_default_params(&q);
+  q.mode = SOCFV_PINNED;
+  q.s_in = 0.0;
+  q.s_eq = 1.0;
+  q.Da = 0.0;
+  socfv_stats s{};
+  int r = socfv_solve_soc_steady(c, &q, nullptr, s_out, &s, hip_stream);
+  if (st) *st = s;
+  if (U_mt && r >= 0) *U_mt = s.U;
+  return r;
+}
+
+int socfv_evaluate(socfv_ctx *c, const socfv_params *p, const double *s, socfv_stats *st,
+                   void *hip_stream) {
+  if (!c || !st) return fail(SOCFV_INVALID_ARG, "NULL argument");
+  TRY(check_params(p));
+  if (!c->have_velocity) return fail(SOCFV_INVALID_ARG, "velocity not set");
+  if (!s) {
+    if (!c->have_state) return fail(SOCFV_INVALID_ARG, "no state in this context");
+    s = c->s64[c->state_buf];
+  }
+  TRY(enter(c, hip_stream));
+  socfv_stats o{};
+  TRY(eval_outputs(c, p, s, &o));
+  TRY(leave(c, hip_stream));
+  st->U = o.U; st->s_out = o.s_out; st->flux_in = o.flux_in; st->flux_in_adv = o.flux_in_adv;
+  st->flux_out = o.flux_out; st->reaction = o.reaction; st->sum_R = o.sum_R; st->q_out = o.q_out;
+  st->residual = o.residual; st->tau = o.tau;
+  return SOCFV_OK;
+}
+
+int socfv_solve_soc_adjoint(socfv_ctx *c, const socfv_params *p, double *dU_dkappa,
+                            double *dU_dlnq, double *psi_out, socfv_stats *st,
+                            void *hip_stream) {
+  const double t0 = now_s();
+  if (!c) return fail(SOCFV_INVALID_ARG, "NULL context");
+  TRY(check_params(p));
+  if (!c->have_state) return fail(SOCFV_INVALID_ARG, "no forward state: solve first");
+  if (c->last_p.s_in != p->s_in || c->last_p.s_eq != p->s_eq || c->last_p.Da != p->Da ||
+      c->last_p.mode != p->mode || c->last_p.cfl != p->cfl)
+    return fail(SOCFV_INVALID_ARG, "parameters differ from the forward solve");
+  TRY(ensure_adjoint(c));
+  TRY(enter(c, hip_stream));
+  Solver S{c, p};
+  TRY(S.setup());
+  const long long n = c->g.n;
+  const int pinned = p->mode == SOCFV_PINNED;
+  // g_P = w_out,P / (Q_out (s_eq - s_in)); Q_out from the outputs of the forward state
+  socfv_stats o{};
+  TRY(eval_outputs(c, p, c->s64[c->state_buf], &o));
+  const double gscale = 1.0 / (o.q_out * (p->s_eq - p->s_in));
+  double *psi[2] = {c->aux64, c->aux64b};
+  launch_fill_f64(psi[0], n, 0.0, c->st);
+  launch_fill_f64(psi[1], n, 0.0, c->st);
+  const int K = S.chunk_len();
+  double out[NV];
+  // relative residual ||g - A^T psi|| / ||g||, ||g|| from psi = 0
+  auto adj_refresh = [&](int src, int dst, const float *delta) -> int {
+    AdjRefreshArgs a;
+    a.g = c->g; a.flags = c->flags; a.w = faces64(c); a.kappa = c->kappa;
+    a.psi64 = psi[src]; a.delta = delta; a.psi64_new = psi[dst]; a.r0 = c->r0;
+    a.Da = p->Da; a.gscale = gscale; a.pinned = pinned; a.partial = c->partial; a.zc = S.t.zc;
+    launch_adj_refresh(a, S.t, c->st);
+    HIPCHK(hipGetLastError());
+    ++S.it64;
+    return reduce_to_host(c, (int)S.nblk, NV, 0u, out);
+  };
+  TRY(adj_refresh(0, 1, nullptr));
+  int cur = 1;
+  const double gnorm = std::sqrt(out[0]);
+  if (!(gnorm > 0)) return fail(SOCFV_INVALID_ARG, "zero adjoint right-hand side");
+  double rel = 1.0;
+  int status = SOCFV_NOT_CONVERGED;
+  auto adj_chunk = [&](auto *b0, auto *b1, int &cc, int k, bool dc, auto w, double gs) -> int {
+    using T = std::remove_pointer_t<decltype(b0)>;
+    T *b[2] = {b0, b1};
+    for (int j = 0; j < k; ++j) {
+      AdjointArgs<T> a;
+      a.g = c->g; a.flags = c->flags; a.w = w; a.kappa = c->kappa;
+      a.psi = b[cc]; a.psi_new = b[cc ^ 1]; a.r0 = dc ? c->r0 : nullptr;
+      a.dt = (T)S.dt; a.Da = (T)p->Da; a.gscale = (T)gs; a.pinned = pinned;
+      a.partial = j == k - 1 ? c->partial : nullptr; a.zc = S.t.zc;
+      launch_adjoint<T>(a, S.t, c->st);
+      cc ^= 1;
+    }
+    HIPCHK(hipGetLastError());
+    return reduce_to_host(c, (int)S.nblk, NV, 0u, out);
+  };
+  if (p->precision == SOCFV_FP64) {
+    while (S.it < p->max_iter) {
+      long k = std::min<long>(K, p->max_iter - S.it);
+      TRY(adj_chunk(psi[0], psi[1], cur, (int)k, false, faces64(c), gscale));
+      S.it += k;
+      S.it64 += k;
+      rel = std::sqrt(out[0]) / gnorm;
+      if (!std::isfinite(rel) || out[1] > 0) return fail(SOCFV_DIVERGED, "adjoint diverged");
+      if (rel < p->tol) { status = SOCFV_OK; break; }
+    }
+  } else {
+    rel = 1.0;
+    while (rel >= p->tol && S.it < p->max_iter) {
+      launch_fill_f32(c->s32[0], n, 0.0f, c->st);
+      launch_fill_f32(c->s32[1], n, 0.0f, c->st);
+      int cd = 0;
+      const double target = std::fmax(0.5 * p->tol, 1e-4 * rel);
+      double best = INFINITY;
+      int stall = 0;
+      while (S.it < p->max_iter) {
+        long k = std::min<long>(K, p->max_iter - S.it);
+        TRY(adj_chunk(c->s32[0], c->s32[1], cd, (int)k, true, faces32(c), 0.0));
+        S.it += k;
+        S.it32 += k;
+        const double ri = std::sqrt(out[0]) / gnorm;
+        if (!std::isfinite(ri) || out[1] > 0) return fail(SOCFV_DIVERGED, "adjoint diverged");
+        if (ri < target) break;
+        if (ri < 0.999 * best) { best = ri; stall = 0; }
+        else if (++stall >= 8) break;
+      }
+      TRY(adj_refresh(cur, cur ^ 1, c->s32[cd]));
+      cur ^= 1;
+      ++S.cycles;
+      rel = std::sqrt(out[0]) / gnorm;
+      if (!std::isfinite(rel)) return fail(SOCFV_DIVERGED, "adjoint diverged");
+    }
+    if (rel < p->tol) status = SOCFV_OK;
+  }
+  // gradients
+  const int gb = outputs_blocks(c->g);
+  TRY(ensure_partial(c, (long long)gb * NV + 64));
+  launch_gradients(c->g, c->flags, faces64(c), c->s64[c->state_buf], psi[cur], p->s_in, p->s_eq,
+                   p->Da, pinned, dU_dkappa, c->partial, gb, c->st);
+  HIPCHK(hipGetLastError());
+  double gsum[NV];
+  TRY(reduce_to_host(c, gb, NV, 0u, gsum));
+  if (dU_dlnq) *dU_dlnq = gsum[0];
+  if (psi_out)
+    HIPCHK(hipMemcpyAsync(psi_out, psi[cur], sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice,
+                          c->st));
+  TRY(leave(c, hip_stream));
+  if (st) {
+    socfv_stats s{};
+    s.iterations = S.it; s.it_fp32 = S.it32; s.it_fp64 = S.it64; s.cycles = S.cycles;
+    s.status = status; s.residual = rel; s.dt = S.dt; s.tau = S.tau; s.U = o.U;
+    s.seconds = now_s() - t0;
+    *st = s;
+  }
+  if (status == SOCFV_NOT_CONVERGED) fail(status, "adjoint not converged (relative residual %g)", rel);
+  return status;
+}
+
+int socfv_set_tiles(socfv_ctx *c, int tile_y, int z_chunk) {
+  if (!c) return fail(SOCFV_INVALID_ARG, "NULL context");
+  if (tile_y != 0) {
+    if (tile_y < 1 || tile_y > 16 || (tile_y & (tile_y - 1)))
+      return fail(SOCFV_INVALID_ARG, "tile_y must be a power of two in [1, 16]");
+    c->tiles.ty = tile_y;
+    if (z_chunk == 0) c->tiles = auto_tiles(c->g, tile_y);
+  }
+  if (z_chunk != 0) {
+    if (z_chunk < 1 || z_chunk > 1024) return fail(SOCFV_INVALID_ARG, "z_chunk must be in [1, 1024]");
+    c->tiles.zc = z_chunk;
+  }
+  c->tiles_fixed = true;
+  return ensure_partial(c, (long long)NV * sweep_blocks(c->g, c->tiles) + 64);
+}
+
+int socfv_autotune(socfv_ctx *c, int sweeps, int best[3], void *hip_stream) {
+  if (!c) return fail(SOCFV_INVALID_ARG, "NULL context");
+  if (!c->have_velocity) return fail(SOCFV_INVALID_ARG, "velocity not set");
+  if (sweeps < 2) sweeps = 2;
+  TRY(ensure_state(c));
+  TRY(enter(c, hip_stream));
+  socfv_params p;
+  socfv_default_params(&p);
+  Solver S{c, &p};
+  TRY(S.setup());
+  const long long n = c->g.n;
+  launch_init_state(c->g, c->flags, nullptr, p.s_in, p.s_eq, 0, c->s64[0], c->st);
+  launch_f64_to_f32(c->s64[0], c->s32[0], n, c->st);
+  launch_fill_f32(c->s32[1], n, 0.0f, c->st);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int tys[] = {1, 2, 4, 8, 16};
+  const int zcs[] = {1, 2, 4, 8, 16, 32, 64};
+  float best_ms = 1e30f;
+  Tiles best_t = c->tiles;
+  for (int ty : tys) {
+    for (int zc : zcs) {
+      if (zc > c->g.nz) continue;
+      Tiles t{ty, zc};
+      S.t = t;
+      S.nblk = sweep_blocks(c->g, t);
+      int cur = 0;
+      // warm-up
+      for (int j = 0; j < 2; ++j) {
+        SweepArgs<float> a = S.sweep_args<float>(c->s32[cur], c->s32[cur ^ 1], false, nullptr);
+        a.w = faces32(c);
+        launch_sweep<float>(a, t, c->st);
+        cur ^= 1;
+      }
+      HIPCHK(hipEventRecord(e0, c->st));
+      for (int j = 0; j < sweeps; ++j) {
+        SweepArgs<float> a = S.sweep_args<float>(c->s32[cur], c->s32[cur ^ 1], false, nullptr);
+        a.w = faces32(c);
+        launch_sweep<float>(a, t, c->st);
+        cur ^= 1;
+      }
+      HIPCHK(hipEventRecord(e1, c->st));
+      HIPCHK(hipEventSynchronize(e1));
+      HIPCHK(hipGetLastError());
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) { best_ms = ms; best_t = t; }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->tiles = best_t;
+  c->tiles_fixed = true;
+  TRY(ensure_partial(c, (long long)NV * sweep_blocks(c->g, c->tiles) + 64));
+  TRY(leave(c, hip_stream));
+  if (best) { best[0] = 64; best[1] = best_t.ty; best[2] = best_t.zc; }
+  return SOCFV_OK;
+}
+
+int socfv_info(const socfv_ctx *c, int dims[3], long counts[3]) {
+  if (!c) return fail(SOCFV_INVALID_ARG, "NULL context");
+  if (dims) { dims[0] = c->g.nx; dims[1] = c->g.ny; dims[2] = c->g.nz; }
+  if (counts) { counts[0] = c->npore; counts[1] = c->nreact; counts[2] = 0; }
+  return SOCFV_OK;
+}
+
+int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
+                      double *const *s_out, socfv_stats *st, void *hip_stream) {
+  // sequential fallback until the batched kernel lands
+  if (n < 0 || (n > 0 && (!ctxs || !p))) return fail(SOCFV_INVALID_ARG, "bad batch arguments");
+  int worst = SOCFV_OK;
+  for (int i = 0; i < n; ++i) {
+    socfv_stats s{};
+    int r = socfv_solve_soc_steady(ctxs[i], &p[i], nullptr, s_out ? s_out[i] : nullptr, &s,
+                                   hip_stream);
+    if (st) st[i] = s;
+    if (r < 0) return r;
+    if (r > worst) worst = r;
+  }
+  return worst;
+}
+
+}  // extern "C"

@@ -1,0 +1,154 @@
+// Internal interface between the HIP kernels (kernels.hip) and the host runtime (api.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace socfv {
+
+// Per-cell flag byte: bits 0..5 = face shared with a fibre voxel (x-, x+, y-, y+, z-, z+),
+// bit 6 = pore cell.  Domain walls are not flagged (they are known from the position).
+constexpr uint8_t FL_XM = 1, FL_XP = 2, FL_YM = 4, FL_YP = 8, FL_ZM = 16, FL_ZP = 32,
+                  FL_FIBRE = 63, FL_PORE = 64;
+
+// Reduction slots (double per block, NV values per block).
+constexpr int NV = 4;
+
+// One problem on the device.  Face velocities are stored per cell for the cell's lower
+// x / y / z face (x = 0 face: inlet; y = 0 and z = 0 faces: walls, zero), plus the outlet
+// plane wxo (ny * nz) for the x = nx faces; upper y / z wall faces are zero by contract.
+template <typename T>
+struct Faces {
+  const T *wx, *wy, *wz, *wxo;
+};
+
+struct Grid {
+  int nx, ny, nz;
+  long long n;          // nx * ny * nz
+};
+
+// Arguments of one explicit sweep.
+template <typename T>
+struct SweepArgs {
+  Grid g;
+  const uint8_t *flags;
+  Faces<T> w;
+  const float *kappa;   // nullable: uniform activity 1
+  const T *s;           // state (or correction) read
+  T *s_new;             // state (or correction) written
+  const float *r0;      // defect correction: frozen FP64 residual in FP32 (else null)
+  T dt, s_in, s_eq, Da; // in the correction form s_in = s_eq = 0
+  int pinned;
+  double lo, hi;        // bound check on the written state (ignored for corrections)
+  double *partial;      // nullable: per-block [sum R^2, violations, sum R, -]
+  int zc;               // z cells per block
+};
+
+// FP64 residual refresh for the defect correction:
+//   t = s64 + delta;  s64_new = t;  r0 = R64(t) (stored FP32); partials of R64.
+struct RefreshArgs {
+  Grid g;
+  const uint8_t *flags;
+  Faces<double> w;
+  const float *kappa;
+  const double *s64;
+  const float *delta;   // nullable: zero correction
+  double *s64_new;
+  float *r0;
+  double s_in, s_eq, Da;
+  int pinned;
+  double lo, hi;
+  double *partial;
+  int zc;
+};
+
+// Adjoint sweep: psi_new = psi + dt (g - A^T psi) (reversed advection).
+template <typename T>
+struct AdjointArgs {
+  Grid g;
+  const uint8_t *flags;
+  Faces<T> w;
+  const float *kappa;
+  const T *psi;
+  T *psi_new;
+  const float *r0;      // correction form: frozen FP64 adjoint residual (else null)
+  T dt, Da, gscale;     // g_P = gscale * w_out,P on outlet cells (0 in correction form)
+  int pinned;
+  double *partial;
+  int zc;
+};
+
+struct AdjRefreshArgs {
+  Grid g;
+  const uint8_t *flags;
+  Faces<double> w;
+  const float *kappa;
+  const double *psi64;
+  const float *delta;
+  double *psi64_new;
+  float *r0;
+  double Da, gscale;
+  int pinned;
+  double *partial;
+  int zc;
+};
+
+// Launch shapes.
+struct Tiles {
+  int ty;   // threads (rows) along y per block; x is one 64-wide wave
+  int zc;   // z cells marched per block
+};
+
+dim3 sweep_grid(const Grid &g, const Tiles &t);
+
+// ---- kernels (launch wrappers; all enqueue on `st`) ---------------------------------
+
+void launch_flags(const Grid &g, const uint8_t *solid, uint8_t *flags, double *partial,
+                  int nblk, hipStream_t st);
+int flags_blocks(const Grid &g);
+
+// velocity ingest: writes FP32 and FP64 per-cell lower faces and the outlet plane.
+// partial per block: [Q_in, max|div|, max|u|, bad-face count]
+void launch_velocity(const Grid &g, const uint8_t *flags, const double *ux, const double *uy,
+                     const double *uz, double q, float *w32[4], double *w64[4],
+                     double *partial, int nblk, hipStream_t st);
+int velocity_blocks(const Grid &g);
+
+// max over updated cells of sum max(w,0) + sum G + lam (partial slot 0, max)
+void launch_maxdiag(const Grid &g, const uint8_t *flags, Faces<double> w, const float *kappa,
+                    double Da, int pinned, double *partial, int nblk, hipStream_t st);
+
+template <typename T>
+void launch_sweep(const SweepArgs<T> &a, const Tiles &t, hipStream_t st);
+void launch_refresh(const RefreshArgs &a, const Tiles &t, hipStream_t st);
+template <typename T>
+void launch_adjoint(const AdjointArgs<T> &a, const Tiles &t, hipStream_t st);
+void launch_adj_refresh(const AdjRefreshArgs &a, const Tiles &t, hipStream_t st);
+
+// outputs of a state: partial per block (NV2 = 8 slots):
+// [sum_out w s, sum_out w, F_in, F_in_adv, reaction, sum_R, sum R^2, -]
+constexpr int NV2 = 8;
+void launch_outputs(const Grid &g, const uint8_t *flags, Faces<double> w, const float *kappa,
+                    const double *s, double s_in, double s_eq, double Da, int pinned,
+                    double *partial, int nblk, hipStream_t st);
+int outputs_blocks(const Grid &g);
+
+// gradients: dU_dkappa and partial [sum psi Radv, -, -, -]
+void launch_gradients(const Grid &g, const uint8_t *flags, Faces<double> w, const double *s,
+                      const double *psi, double s_in, double s_eq, double Da, int pinned,
+                      double *dU_dkappa, double *partial, int nblk, hipStream_t st);
+
+// deterministic second pass: out[k] = sum (or max if bit k of maxmask) over blocks
+void launch_reduce(const double *partial, int nblk, int nv, unsigned maxmask, double *out,
+                   hipStream_t st);
+
+// helpers
+void launch_fill_f32(float *p, long long n, float v, hipStream_t st);
+void launch_fill_f64(double *p, long long n, double v, hipStream_t st);
+void launch_init_state(const Grid &g, const uint8_t *flags, const double *s_init, double s_in,
+                       double s_eq, int pinned, double *s64, hipStream_t st);
+void launch_f64_to_f32(const double *a, float *b, long long n, hipStream_t st);
+void launch_f32_to_f64(const float *a, double *b, long long n, hipStream_t st);
+void launch_mask_held(const Grid &g, const uint8_t *flags, int pinned, double *p, hipStream_t st);
+
+}  // namespace socfv
