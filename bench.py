@@ -1,0 +1,272 @@
+#!/usr/bin/env python3
+"""Benchmark of the steady state-of-charge solve on one MI355X.
+
+Workload (default): the paper-scale single-GPU slab, 1024 x 512 x 256 voxels (134,217,728
+cells; h = 1.25 um as in the paper's logpile run), overlapping fibres of radius 4 voxels
+with random orientations in the y-z plane, porosity 0.78, Darcy face velocities at cell
+Peclet 0.2, 1 and 5 (one flow field scaled three ways).  Finite-rate surface reaction
+Da = 0.45 per fibre face, inlet s = 1, s_eq = 0.
+
+One step = for each of the three flow rates: ingest the velocity (set_velocity), solve to
+steady state at residual 1e-8 (FP32 sweeps on an FP64-refreshed correction, FP64
+reductions, FP64 polish) and evaluate U and the flux balance.  value = cell updates per
+second over the step (all lattice cells, every sweep of every precision), in GLUPS.
+
+Also reported: the live roofline of the dominant kernel (the FP32 correction sweep,
+timed with HIP events on the library's stream inside the timed region), accuracy against
+the FP64 oracle (64 x 32 x 32 exact solve) and against the stored oracle references of
+the 256 x 128 x 128 workload, the adjoint / forward time ratio, and the FP64 CPU oracle
+timed on a bounded sample of the same slab.
+
+    python bench.py [--gpus 1] [--steps 1] [--warmup 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GLUPS & HBM GB/s (% peak) to steady s at residual 1e-8; U_mt err; adjoint/fwd time"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per cell update of the FP32 correction sweep:
+# s in 4 + s out 4 + three lower-face velocities 12 + flag byte 1 + frozen residual 4
+BYTES_FP32_DC = 25
+BYTES_FP64 = 41          # FP64 sweep: 8 + 8 + 24 + 1
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def parse_scale(s):
+    if not s:
+        return None
+    nx, ny, nz = (int(v) for v in s.lower().split("x"))
+    return nx, ny, nz
+
+
+def build_slab(scale, device):
+    from paper_2502_08034_amd import inputs as I
+    cfg = I.WORKLOADS["slab1024"]
+    nx, ny, nz = scale or cfg["shape"]
+    t = time.time()
+    geo = I.fibres_boolean(nx, ny, nz, cfg["radius"], cfg["porosity"], cfg["seed"])
+    log(f"geometry {nx}x{ny}x{nz}: {geo.n_fibres} fibres, porosity {geo.porosity:.4f}, "
+        f"{geo.filled} cells filled, {time.time() - t:.1f}s")
+    t = time.time()
+    u, info = I.darcy_velocity(geo.solid, 1.0, rtol=1e-12, device=device, return_info=True,
+                               log=log, as_numpy=False)
+    log(f"darcy: {info['cg_iterations']} CG iterations, rel residual "
+        f"{info['rel_residual'][0]:.2e}, {time.time() - t:.1f}s")
+    return geo, u, cfg
+
+
+def accuracy_legs(sv):
+    """FP32-mode errors against the FP64 oracle: exact solve at 64x32x32, stored
+    references at 256x128x128."""
+    import oracle
+    from paper_2502_08034_amd import inputs as I
+    out = {}
+    w = I.workload("fibre64")
+    solid = w["solid"]
+    u = w["velocity"][0.5]
+    pb = sv.Problem.create(solid, *u)
+    pore = solid == 0
+    p = sv.params(precision="fp32", tol=1e-10, check_every=100)
+    s, st = sv.solve_soc_steady(pb.ctx, p)
+    op = oracle.Problem(solid, *u, s_in=1.0, s_eq=0.0, Da=0.45)
+    sx = oracle.exact_steady(op)
+    Ux = oracle.outputs(op, sx)["U"]
+    umt, smt, _ = sv.compute_umt(pb.ctx, p, want_state=True)
+    opm = oracle.Problem(solid, *u, s_in=0.0, s_eq=1.0, pinned=True)
+    smx = oracle.exact_steady(opm)
+    umx = oracle.outputs(opm, smx)["U"]
+    out["fibre64"] = {
+        "max_abs_ds": float(np.abs(s.cpu().numpy() - sx)[pore].max()),
+        "U_rel_err": abs(st.U - Ux) / abs(Ux),
+        "U_mt_rel_err": abs(umt - umx) / abs(umx),
+        "U_mt_max_abs_ds": float(np.abs(smt.cpu().numpy() - smx)[pore].max()),
+        "U": st.U, "U_mt": umt, "reference": "oracle sparse direct solve", "tol": 1e-10,
+    }
+    gpath = os.path.join(ROOT, "tests", "golden", "fibre256.json")
+    if os.path.exists(gpath):
+        gold = json.load(open(gpath))
+        w = I.workload("fibre256", with_velocity=False)
+        solid = w["solid"]
+        if hashlib.sha256(solid.tobytes()).hexdigest() != gold["geometry_sha256"]:
+            out["fibre256"] = {"skipped": "geometry differs from the stored references"}
+            return out
+        import torch
+        u = I.darcy_velocity(solid, 1.0, rtol=1e-12, device="cuda", as_numpy=False)
+        pb = sv.Problem.create(solid, *u)
+        idx = np.asarray(gold["sample_index"])
+        res = {}
+        for mode in ("finite", "pinned"):
+            g = gold[mode]
+            p = sv.params(precision="fp32", tol=1e-8, mode=1 if g["pinned"] else 0,
+                          s_in=g["s_in"], s_eq=g["s_eq"], Da=g["Da"])
+            s, st = sv.solve_soc_steady(pb.ctx, p)
+            Ug = g["outputs"]["U"]
+            ds = np.abs(s.view(-1)[torch.as_tensor(idx, device="cuda")].cpu().numpy()
+                        - np.asarray(g["s_sample"])).max()
+            res[mode] = {"U": st.U, "U_ref": Ug, "U_rel_err": abs(st.U - Ug) / abs(Ug),
+                         "one_minus_U_rel_err": abs(st.U - Ug) / max(abs(1 - Ug), 1e-300),
+                         "max_abs_ds_sampled": float(ds), "n_sampled": int(idx.size),
+                         "sweeps": st.iterations, "residual": st.residual}
+        res["reference"] = "stored FP64 oracle solve to residual %.0e" % gold["tol"]
+        out["fibre256"] = res
+    return out
+
+
+def cpu_baseline(geo, u_np, seconds):
+    import oracle
+    ux, uy, uz = u_np
+    op = oracle.Problem(geo.solid, ux, uy, uz, s_in=1.0, s_eq=0.0, Da=0.45)
+    n = geo.solid.size
+    dt = 0.4 / oracle.max_diag(op)
+    s = op.initial_state()
+    t = time.time()
+    s = oracle.iterate(op, s, dt, 1)
+    t1 = time.time() - t
+    m = max(1, int(seconds / max(t1, 1e-3)))
+    t = time.time()
+    s = oracle.iterate(op, s, dt, m)
+    el = time.time() - t
+    return {"value": m * n / el / 1e9, "unit": "GLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{m} FP64 explicit sweeps (plus 1 untimed) of the {geo.solid.shape[2]}x"
+                      f"{geo.solid.shape[1]}x{geo.solid.shape[0]} slab at Peclet 1 from s = s_in "
+                      f"({el:.1f} s); per-sweep rate, not run to steady state"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", default=None, help="override box, e.g. 256x128x64")
+    ap.add_argument("--peclet", default="0.2,1,5")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2502_08034_amd import socfv as sv
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    pes = [float(v) for v in args.peclet.split(",")]
+    geo, u1, cfg = build_slab(parse_scale(args.scale), "cuda")
+    nz, ny, nx = geo.solid.shape
+    ncell = nx * ny * nz
+    t = time.time()
+    pb = sv.Problem.create(geo.solid, *u1)
+    info = pb.ctx.info()
+    log(f"setup_geometry + set_velocity: {time.time() - t:.1f}s, {info['pore']} pore cells, "
+        f"{info['reactive']} reactive")
+    tiles = None
+    if args.autotune:
+        tiles = sv.autotune(pb.ctx, sweeps=10)
+        log(f"autotuned tiles {tiles}")
+    p = sv.params(precision="fp32", tol=args.tol, check_every=200)
+
+    def step(tag):
+        per = []
+        for pe in pes:
+            pb.set_flow_rate(pe)
+            _, st = sv.solve_soc_steady(pb.ctx, p, want_state=False)
+            if st.status != sv.OK:
+                raise RuntimeError(f"Pe {pe}: status {st.status}")
+            per.append((pe, st))
+            log(f"{tag} Pe={pe}: {st.iterations} sweeps ({st.it_fp32} fp32, {st.it_fp64} fp64, "
+                f"{st.cycles} refreshes), res {st.residual:.2e}, U={st.U:.10f}, {st.seconds:.2f}s")
+        pb.q = None                     # force re-ingest at the next step
+        return per
+
+    for w in range(args.warmup):
+        step(f"warmup {w}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for k in range(args.steps):
+        runs.append(step(f"step {k}"))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sweeps = sum(st.iterations for r in runs for _, st in r)
+    glups = sweeps * ncell / elapsed / 1e9
+    ms32 = sum(st.ms_fp32 for r in runs for _, st in r)
+    n32 = sum(st.it_fp32 for r in runs for _, st in r)
+    ms64 = sum(st.ms_fp64 for r in runs for _, st in r)
+    n64 = sum(st.sweeps_fp64 for r in runs for _, st in r)
+    avg32 = ms32 / n32 if n32 else float("nan")
+    achieved = BYTES_FP32_DC * ncell / (avg32 / 1e3) / 1e9 if n32 else 0.0
+    last = {f"{pe:g}": {"U": st.U, "sweeps": st.iterations, "residual": st.residual,
+                        "seconds": st.seconds, "balance_rel": abs(st.flux_in - st.flux_out
+                                                                  - st.reaction - st.sum_R)
+                        / abs(st.flux_in)}
+            for pe, st in runs[-1]}
+    result = {
+        "metric": METRIC, "value": glups, "unit": "GLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"fibre slab {nx}x{ny}x{nz} (boolean fibres r=4 in the y-z plane, "
+                               f"porosity {geo.porosity:.3f}), Darcy velocity at cell Peclet "
+                               f"{'/'.join(f'{v:g}' for v in pes)}, Da 0.45/face, FP32 "
+                               f"correction sweeps + FP64 refresh/polish/reductions to residual "
+                               f"{args.tol:g}",
+                   "cells": ncell, "pore_cells": info["pore"], "precision": "fp32+fp64",
+                   "tiles": list(tiles) if tiles else None},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_sweep<float, correction> (FP32 sweep on the correction)",
+                     "bytes_per_cell_update": BYTES_FP32_DC, "avg_sweep_ms": avg32,
+                     "sweeps_timed": n32},
+        "fp64_sweep": {"avg_ms": ms64 / n64 if n64 else None,
+                       "achieved_GBs": BYTES_FP64 * ncell / (ms64 / n64 / 1e3) / 1e9 if n64 else None},
+        "glups_pore_only": glups * info["pore"] / ncell,
+        "per_peclet": last,
+    }
+    if not args.no_adjoint:
+        pe = 1.0 if 1.0 in pes else pes[0]
+        pb.set_flow_rate(pe)
+        _, stf = sv.solve_soc_steady(pb.ctx, p, want_state=False)
+        t = time.perf_counter()
+        _, dlnq, _, sta = sv.solve_soc_adjoint(pb.ctx, p, want_grad=True)
+        torch.cuda.synchronize()
+        ta = time.perf_counter() - t
+        result["adjoint"] = {"peclet": pe, "seconds": ta, "forward_seconds": stf.seconds,
+                             "adjoint_fwd_ratio": ta / stf.seconds, "sweeps": sta.iterations,
+                             "forward_sweeps": stf.iterations, "dU_dlnq": dlnq,
+                             "status": sta.status}
+        log(f"adjoint Pe={pe}: {ta:.2f}s vs forward {stf.seconds:.2f}s")
+    if not args.no_accuracy:
+        t = time.time()
+        result["accuracy"] = accuracy_legs(sv)
+        log(f"accuracy legs {time.time() - t:.1f}s: {json.dumps(result['accuracy'])[:300]}")
+    if not args.no_cpu_baseline:
+        t = time.time()
+        u_np = tuple(a.cpu().numpy() for a in u1)
+        result["cpu_baseline"] = cpu_baseline(geo, u_np, args.cpu_seconds)
+        log(f"cpu baseline {time.time() - t:.1f}s: {result['cpu_baseline']}")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -105,7 +105,10 @@ typedef struct {
   double sum_R;       /* sum of R over updated cells: flux_in - flux_out - reaction */
   double q_out;       /* outlet flow, sum_out w */
   double seconds;     /* wall time of the call */
-  double max_abs_s_change_fp32; /* FP32_PLAIN: last max |dt R| seen (stagnation diagnostic) */
+  double ms_fp32;     /* GPU time of the FP32 sweeps (HIP events around each chunk) */
+  double ms_fp64;     /* GPU time of the FP64 sweeps (excluding refreshes) */
+  double ms_refresh;  /* GPU time of the FP64 residual refreshes */
+  long sweeps_fp64;   /* FP64 sweeps excluding refreshes */
 } socfv_stats;
 
 /* Fill p with defaults: s_in 1, s_eq 0, Da 0.45, FINITE_RATE, FP32, cfl 0.4, tol 1e-8,
@@ -166,14 +169,17 @@ int socfv_evaluate(socfv_ctx *c, const socfv_params *p, const double *s, socfv_s
 
 /*
  * Discrete adjoint of U at the last steady state of this context (which must come from
- * socfv_solve_soc_steady with the same p): solves A^T psi = dU/ds by the same explicit
- * iteration with reversed advection (psi <- psi + dt (g - A^T psi)), to
- * ||g - A^T psi|| / ||g|| < p->tol_adjoint... (p->tol is used), then
+ * socfv_solve_soc_steady with the same s_in, s_eq, Da, mode and cfl): solves
+ * A^T psi = g, g = dU/ds (g_P = w_out,P / (Q_out (s_eq - s_in)) on outlet cells), by the
+ * same explicit iteration with reversed advection, psi <- psi + dt (g - A^T psi), until
+ * ||g - A^T psi||_2 / ||g||_2 < p->tol (FP64 sweeps, or FP32 sweeps on a correction
+ * against FP64 refreshes, by p->precision).  Then
  *   dU_dkappa[P] = Da n_f(P) psi_P (s_eq - s_P)   (device FP64 (nz,ny,nx), nullable;
  *                                                 FINITE_RATE only, 0 elsewhere)
- *   *dU_dlnq     = sum_P psi_P Radv_P(s)          (host; derivative in ln q, u = q u0:
+ *   *dU_dlnq     = sum_P psi_P Radv_P(s)          (host; derivative in ln q for u = q u0:
  *                                                 divide by q for dU/dq)
- * psi_out (device FP64, nullable) receives psi.  Held cells (PINNED) get psi = 0.
+ * with Radv the advective part of R.  psi_out (device FP64, nullable) receives psi; held
+ * cells (PINNED) get psi = 0 (no design variable enters their rows).
  */
 int socfv_solve_soc_adjoint(socfv_ctx *c, const socfv_params *p, double *dU_dkappa,
                             double *dU_dlnq, double *psi_out, socfv_stats *st,

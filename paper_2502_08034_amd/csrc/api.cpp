@@ -61,6 +61,7 @@ struct socfv_ctx {
   Grid g{};
   hipStream_t st = nullptr;      // library stream (default priority)
   hipEvent_t ev = nullptr;
+  hipEvent_t t0 = nullptr, t1 = nullptr;   // timing events around sweep chunks
   uint8_t *flags = nullptr;
   float *w32[4] = {nullptr, nullptr, nullptr, nullptr};
   double *w64[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -178,8 +179,9 @@ struct Solver {
   int pinned;
   double dt = 0, tau = 0;
   double lo = 0, hi = 0;
-  long it = 0, it32 = 0, it64 = 0;
+  long it = 0, it32 = 0, it64 = 0, sw64 = 0;
   int cycles = 0;
+  double ms32 = 0, ms64 = 0, msref = 0;
   Tiles t;
   long long nblk = 0;
 
@@ -230,14 +232,20 @@ struct Solver {
   template <typename T>
   int chunk(T *buf0, T *buf1, int &cur, int k, bool dc, Faces<T> w, double out[NV]) {
     T *buf[2] = {buf0, buf1};
+    HIPCHK(hipEventRecord(c->t0, c->st));
     for (int j = 0; j < k; ++j) {
       SweepArgs<T> a = sweep_args<T>(buf[cur], buf[cur ^ 1], dc, j == k - 1 ? c->partial : nullptr);
       a.w = w;
       launch_sweep<T>(a, t, c->st);
       cur ^= 1;
     }
+    HIPCHK(hipEventRecord(c->t1, c->st));
     HIPCHK(hipGetLastError());
-    return reduce_to_host(c, (int)nblk, NV, 0u, out);
+    TRY(reduce_to_host(c, (int)nblk, NV, 0u, out));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, c->t0, c->t1));
+    (sizeof(T) == 4 ? ms32 : ms64) += ms;
+    return 0;
   }
 
   // FP64 refresh: s64[dst] = s64[src] + delta; r0 = R64; returns res and violations
@@ -259,10 +267,16 @@ struct Solver {
     a.hi = hi;
     a.partial = c->partial;
     a.zc = t.zc;
+    HIPCHK(hipEventRecord(c->t0, c->st));
     launch_refresh(a, t, c->st);
+    HIPCHK(hipEventRecord(c->t1, c->st));
     HIPCHK(hipGetLastError());
     ++it64;
-    return reduce_to_host(c, (int)nblk, NV, 0u, out);
+    TRY(reduce_to_host(c, (int)nblk, NV, 0u, out));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, c->t0, c->t1));
+    msref += ms;
+    return 0;
   }
 
   int check(const double out[NV], double res) {
@@ -289,6 +303,7 @@ struct Solver {
       done += k;
       it += k;
       it64 += k;
+      sw64 += k;
       res = res_of(out[0]);
       TRY(check(out, res));
       if (res < p->tol) { status = SOCFV_OK; break; }
@@ -447,6 +462,8 @@ void socfv_destroy(socfv_ctx *c) {
   hfree(c->dres);
   if (c->hres) (void)hipHostFree(c->hres);
   if (c->ev) (void)hipEventDestroy(c->ev);
+  if (c->t0) (void)hipEventDestroy(c->t0);
+  if (c->t1) (void)hipEventDestroy(c->t1);
   if (c->st) (void)hipStreamDestroy(c->st);
   delete c;
 }
@@ -464,7 +481,8 @@ int socfv_setup_geometry(socfv_ctx **out, int nx, int ny, int nz, const uint8_t 
   c->tiles = auto_tiles(c->g, 4);
   auto bail = [&](int code) { socfv_destroy(c); return code; };
   if (hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess)
+      hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreate(&c->t0) != hipSuccess || hipEventCreate(&c->t1) != hipSuccess)
     return bail(fail(SOCFV_HIP_ERROR, "stream/event creation failed"));
   if (hipMalloc(&c->flags, (size_t)n) != hipSuccess ||
       hipMalloc(&c->dres, sizeof(double) * 64) != hipSuccess ||
@@ -597,6 +615,10 @@ int socfv_solve_soc_steady(socfv_ctx *c, const socfv_params *p, const double *s_
   s.it_fp64 = S.it64;
   s.cycles = S.cycles;
   s.status = status;
+  s.ms_fp32 = S.ms32;
+  s.ms_fp64 = S.ms64;
+  s.ms_refresh = S.msref;
+  s.sweeps_fp64 = S.sw64;
   s.dt = S.dt;
   s.tau = S.tau;
   s.residual = p->precision == SOCFV_FP64 ? res : s.residual;

@@ -175,13 +175,14 @@ def fill_disconnected(geo: Geometry) -> Geometry:
 # ---------------------------------------------------------------------------------
 
 def darcy_velocity(solid, peclet, rtol=1e-12, device=None, max_iter=400000,
-                   return_info=False, log=None):
+                   return_info=False, log=None, as_numpy=True):
     """Face velocities of the Darcy pressure-Laplace flow, scaled to cell Peclet ``peclet``.
 
     ``solid`` is one (nz, ny, nx) mask or a list of masks (boxes may differ; they are
     padded with solid voxels to a common box and solved as one batch, each problem with
-    its own CG scalars and its own outlet plane).  Returns float64 numpy arrays
-    ``(ux, uy, uz)``, or a list of them for a list input.
+    its own CG scalars and its own outlet plane).  Returns float64 arrays ``(ux, uy, uz)``
+    (numpy, or contiguous torch tensors on ``device`` with ``as_numpy=False``), or a list of
+    them for a list input.
     """
     import torch
     batched = isinstance(solid, (list, tuple))
@@ -284,9 +285,10 @@ def darcy_velocity(solid, peclet, rtol=1e-12, device=None, max_iter=400000,
         Q = float(ux[b, :mz, :my, 0].sum())
         phi = float((m == 0).mean())
         scale = pes[b] / ((Q / (my * mz)) / phi)
-        out.append((ux[b, :mz, :my, :mx + 1].mul(scale).cpu().numpy(),
-                    uy[b, :mz, :my + 1, :mx].mul(scale).cpu().numpy(),
-                    uz[b, :mz + 1, :my, :mx].mul(scale).cpu().numpy()))
+        trip = (ux[b, :mz, :my, :mx + 1].mul(scale).contiguous(),
+                uy[b, :mz, :my + 1, :mx].mul(scale).contiguous(),
+                uz[b, :mz + 1, :my, :mx].mul(scale).contiguous())
+        out.append(tuple(t.cpu().numpy() for t in trip) if as_numpy else trip)
     info = {"cg_iterations": it, "rel_residual": [float(v) for v in rel_true]}
     res = out if batched else out[0]
     return (res, info) if return_info else res

@@ -36,8 +36,9 @@ class Stats(C.Structure):
                 ("dt", C.c_double), ("tau", C.c_double), ("U", C.c_double),
                 ("s_out", C.c_double), ("flux_in", C.c_double), ("flux_in_adv", C.c_double),
                 ("flux_out", C.c_double), ("reaction", C.c_double), ("sum_R", C.c_double),
-                ("q_out", C.c_double), ("seconds", C.c_double),
-                ("max_abs_s_change_fp32", C.c_double)]
+                ("q_out", C.c_double), ("seconds", C.c_double), ("ms_fp32", C.c_double),
+                ("ms_fp64", C.c_double), ("ms_refresh", C.c_double),
+                ("sweeps_fp64", C.c_long)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
