@@ -18,7 +18,7 @@ the FP64 oracle (64 x 32 x 32 exact solve) and against the stored oracle referen
 the 256 x 128 x 128 workload, the adjoint / forward time ratio, and the FP64 CPU oracle
 timed on a bounded sample of the same slab.
 
-    python bench.py [--gpus 1] [--steps 1] [--warmup 1]
+    python bench.py [--gpus 1] [--steps 1] [--warmup 0]
 """
 from __future__ import annotations
 
@@ -152,7 +152,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--scale", default=None, help="override box, e.g. 256x128x64")
     ap.add_argument("--peclet", default="0.2,1,5")
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -161,6 +161,10 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--tiles", default=None, help="tile_y,z_chunk for the sweeps")
+    ap.add_argument("--profile-sweeps", type=int, default=0,
+                    help="profiling run: a plain copy of known size, then this many FP32 "
+                         "correction sweeps at Peclet 1 on the slab, and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -171,6 +175,15 @@ def main():
     from paper_2502_08034_amd import socfv as sv
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.profile_sweeps:
+        # counter calibration, first kernels of the process: 4 converting copies of 2^28
+        # FP32 values to FP64 (1 GiB read, 2 GiB written each)
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        c = torch.empty(1 << 28, dtype=torch.float64, device="cuda")
+        for _ in range(4):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        del a, c
     pes = [float(v) for v in args.peclet.split(",")]
     geo, u1, cfg = build_slab(parse_scale(args.scale), "cuda")
     nz, ny, nx = geo.solid.shape
@@ -181,6 +194,20 @@ def main():
     log(f"setup_geometry + set_velocity: {time.time() - t:.1f}s, {info['pore']} pore cells, "
         f"{info['reactive']} reactive")
     tiles = None
+    if args.tiles:
+        vals = [int(v) for v in args.tiles.split(",")] + [0, 0, -1]
+        ty, zc, zc2, two = vals[:4]
+        sv.set_tiles(pb.ctx, ty, zc, zc2, two)
+        tiles = (ty, zc, zc2, two)
+    if args.profile_sweeps:
+        pb.set_flow_rate(1.0)
+        pp = sv.params(precision="fp32", tol=0.0, max_iter=args.profile_sweeps, check_every=200)
+        _, st = sv.solve_soc_steady(pb.ctx, pp, want_state=False)
+        avg = st.ms_fp32 / max(st.it_fp32, 1)
+        print(json.dumps({"profile_sweeps": st.it_fp32, "avg_sweep_ms": avg,
+                          "achieved_GBs": BYTES_FP32_DC * ncell / (avg / 1e3) / 1e9,
+                          "cells": ncell, "tiles": tiles}), flush=True)
+        return
     if args.autotune:
         tiles = sv.autotune(pb.ctx, sweeps=10)
         log(f"autotuned tiles {tiles}")
@@ -199,6 +226,9 @@ def main():
         pb.q = None                     # force re-ingest at the next step
         return per
 
+    # untimed priming: allocates the solver buffers and loads every kernel once
+    sv.solve_soc_steady(pb.ctx, sv.params(precision="fp32", tol=0.0, max_iter=400,
+                                          check_every=200), want_state=False)
     for w in range(args.warmup):
         step(f"warmup {w}")
     torch.cuda.synchronize()
@@ -235,7 +265,7 @@ def main():
                    "tiles": list(tiles) if tiles else None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sweep<float, correction> (FP32 sweep on the correction)",
+                     "kernel": "k_sweep_v4<correction> (FP32 correction sweep, one per launch)",
                      "bytes_per_cell_update": BYTES_FP32_DC, "avg_sweep_ms": avg32,
                      "sweeps_timed": n32},
         "fp64_sweep": {"avg_ms": ms64 / n64 if n64 else None,

@@ -196,12 +196,14 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
                       double *const *s_out, socfv_stats *st, void *hip_stream);
 
 /*
- * Tile shapes.  The stencil sweeps work on (tile_x x tile_y) columns of cells marching
- * z_chunk cells along z.  socfv_set_tiles overrides them for a context (0 = keep);
- * socfv_autotune times the candidate shapes on this context's problem (FP32 sweeps,
- * `sweeps` each) and keeps the fastest; best[3] (host, nullable) receives it.
+ * Launch shapes.  Single sweeps work on (64 x tile_y) lanes marching z_chunk cells along z;
+ * with two_sweeps set, FP32 sweeps on grids with even nx run two sweeps per launch on
+ * 64 x 16 lanes marching z_chunk2 cells (off by default).  socfv_set_tiles overrides them for a
+ * context (0 = keep, two_sweeps < 0 = keep); socfv_autotune times candidate shapes on this
+ * context's problem (`sweeps` sweeps each) and keeps the fastest; best[3] (host, nullable)
+ * receives tile_y, z_chunk, z_chunk2.
  */
-int socfv_set_tiles(socfv_ctx *c, int tile_y, int z_chunk);
+int socfv_set_tiles(socfv_ctx *c, int tile_y, int z_chunk, int z_chunk2, int two_sweeps);
 int socfv_autotune(socfv_ctx *c, int sweeps, int best[3], void *hip_stream);
 
 /* Problem facts: dims[3] = nx, ny, nz; counts[3] = pore cells, reactive cells,

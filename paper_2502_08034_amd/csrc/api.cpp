@@ -78,7 +78,7 @@ struct socfv_ctx {
   long npore = 0, nreact = 0, ninlet = 0, noutlet = 0;
   bool have_velocity = false;
   double Q_in = 0, div_max = 0, u_max = 0;
-  Tiles tiles{4, 8};
+  Tiles tiles{4, 8, 32, 0};
   bool tiles_fixed = false;
   // last forward solution
   bool have_state = false;
@@ -97,12 +97,27 @@ Tiles auto_tiles(const Grid &g, int ty) {
   if (zc < 1) zc = 1;
   if (zc > 32) zc = 32;
   if (zc > g.nz) zc = g.nz;
-  return Tiles{ty, (int)zc};
+  // two-sweep kernel: enough blocks to fill the chip, long z marches (2 extra planes each)
+  long long t2 = (long long)((g.nx + 123) / 124) * ((g.ny + 13) / 14);
+  long long zc2 = t2 > 0 ? (long long)g.nz * t2 / 1024 : g.nz;
+  if (zc2 < 8) zc2 = 8;
+  if (zc2 > 64) zc2 = 64;
+  if (zc2 > g.nz) zc2 = g.nz;
+  return Tiles{ty, (int)zc, (int)zc2, 0};
 }
 
 long long sweep_blocks(const Grid &g, const Tiles &t) {
   dim3 d = sweep_grid(g, t);
   return (long long)d.x * d.y * d.z;
+}
+
+// doubles of per-block partials any sweep launch of this problem can write
+long long partial_need(const Grid &g, const Tiles &t) {
+  dim3 a = sweep_grid(g, t), b = sweep_grid_v4(g, t), c = sweep2_grid(g, t);
+  long long m = (long long)a.x * a.y * a.z;
+  m = std::max(m, (long long)b.x * b.y * b.z);
+  m = std::max(m, (long long)c.x * c.y * c.z);
+  return NV * m + 64;
 }
 
 int ensure_partial(socfv_ctx *c, long long doubles) {
@@ -147,7 +162,7 @@ int ensure_state(socfv_ctx *c) {
     if (!c->s32[k]) HIPCHK(hipMalloc(&c->s32[k], sizeof(float) * n));
   }
   if (!c->r0) HIPCHK(hipMalloc(&c->r0, sizeof(float) * n));
-  return ensure_partial(c, (long long)NV * sweep_blocks(c->g, c->tiles) + 64);
+  return ensure_partial(c, partial_need(c->g, c->tiles));
 }
 
 int ensure_adjoint(socfv_ctx *c) {
@@ -232,16 +247,37 @@ struct Solver {
   template <typename T>
   int chunk(T *buf0, T *buf1, int &cur, int k, bool dc, Faces<T> w, double out[NV]) {
     T *buf[2] = {buf0, buf1};
+    const bool two = sizeof(T) == 4 && two_path(c->g) && t.two;
+    long long nb = nblk;
     HIPCHK(hipEventRecord(c->t0, c->st));
-    for (int j = 0; j < k; ++j) {
+    int j = 0;
+    if (two) {
+      // two sweeps per launch; an odd remainder ends with one single sweep
+      for (; j + 1 < k; j += 2) {
+        const bool lastl = j + 2 >= k;
+        SweepArgs<T> a = sweep_args<T>(buf[cur], buf[cur ^ 1], dc, lastl ? c->partial : nullptr);
+        a.w = w;
+        launch_sweep2(reinterpret_cast<const SweepArgs<float> &>(a), t, c->st);
+        cur ^= 1;
+      }
+      dim3 g2 = sweep2_grid(c->g, t);
+      nb = (long long)g2.x * g2.y * g2.z;
+    }
+    for (; j < k; ++j) {
       SweepArgs<T> a = sweep_args<T>(buf[cur], buf[cur ^ 1], dc, j == k - 1 ? c->partial : nullptr);
       a.w = w;
       launch_sweep<T>(a, t, c->st);
       cur ^= 1;
+      if (sizeof(T) == 4 && vec4_path(c->g)) {
+        dim3 gv = sweep_grid_v4(c->g, t);
+        nb = (long long)gv.x * gv.y * gv.z;
+      } else {
+        nb = nblk;
+      }
     }
     HIPCHK(hipEventRecord(c->t1, c->st));
     HIPCHK(hipGetLastError());
-    TRY(reduce_to_host(c, (int)nblk, NV, 0u, out));
+    TRY(reduce_to_host(c, (int)nb, NV, 0u, out));
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, c->t0, c->t1));
     (sizeof(T) == 4 ? ms32 : ms64) += ms;
@@ -478,7 +514,7 @@ int socfv_setup_geometry(socfv_ctx **out, int nx, int ny, int nz, const uint8_t 
   if (n > (1ll << 40)) return fail(SOCFV_INVALID_ARG, "grid too large");
   socfv_ctx *c = new socfv_ctx();
   c->g = Grid{nx, ny, nz, n};
-  c->tiles = auto_tiles(c->g, 4);
+  c->tiles = auto_tiles(c->g, 16);
   auto bail = [&](int code) { socfv_destroy(c); return code; };
   if (hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess ||
@@ -782,20 +818,27 @@ int socfv_solve_soc_adjoint(socfv_ctx *c, const socfv_params *p, double *dU_dkap
   return status;
 }
 
-int socfv_set_tiles(socfv_ctx *c, int tile_y, int z_chunk) {
+int socfv_set_tiles(socfv_ctx *c, int tile_y, int z_chunk, int z_chunk2, int two_sweeps) {
   if (!c) return fail(SOCFV_INVALID_ARG, "NULL context");
   if (tile_y != 0) {
     if (tile_y < 1 || tile_y > 16 || (tile_y & (tile_y - 1)))
       return fail(SOCFV_INVALID_ARG, "tile_y must be a power of two in [1, 16]");
+    Tiles t = auto_tiles(c->g, tile_y);
     c->tiles.ty = tile_y;
-    if (z_chunk == 0) c->tiles = auto_tiles(c->g, tile_y);
+    if (z_chunk == 0) c->tiles.zc = t.zc;
   }
   if (z_chunk != 0) {
-    if (z_chunk < 1 || z_chunk > 1024) return fail(SOCFV_INVALID_ARG, "z_chunk must be in [1, 1024]");
+    if (z_chunk < 1 || z_chunk > 4096) return fail(SOCFV_INVALID_ARG, "z_chunk must be in [1, 4096]");
     c->tiles.zc = z_chunk;
   }
+  if (z_chunk2 != 0) {
+    if (z_chunk2 < 1 || z_chunk2 > 4096)
+      return fail(SOCFV_INVALID_ARG, "z_chunk2 must be in [1, 4096]");
+    c->tiles.zc2 = z_chunk2;
+  }
+  if (two_sweeps >= 0) c->tiles.two = two_sweeps ? 1 : 0;
   c->tiles_fixed = true;
-  return ensure_partial(c, (long long)NV * sweep_blocks(c->g, c->tiles) + 64);
+  return ensure_partial(c, partial_need(c->g, c->tiles));
 }
 
 int socfv_autotune(socfv_ctx *c, int sweeps, int best[3], void *hip_stream) {
@@ -822,7 +865,7 @@ int socfv_autotune(socfv_ctx *c, int sweeps, int best[3], void *hip_stream) {
   for (int ty : tys) {
     for (int zc : zcs) {
       if (zc > c->g.nz) continue;
-      Tiles t{ty, zc};
+      Tiles t{ty, zc, c->tiles.zc2, c->tiles.two};
       S.t = t;
       S.nblk = sweep_blocks(c->g, t);
       int cur = 0;
@@ -850,11 +893,41 @@ int socfv_autotune(socfv_ctx *c, int sweeps, int best[3], void *hip_stream) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  // two-sweep kernel: z chunk
+  float best2 = 1e30f;
+  int best_zc2 = c->tiles.zc2;
+  if (two_path(c->g)) {
+    const int zc2s[] = {8, 16, 32, 64, 128};
+    for (int zc2 : zc2s) {
+      if (zc2 > c->g.nz && zc2 != 8) continue;
+      Tiles t = best_t;
+      t.zc2 = zc2;
+      int cur = 0;
+      SweepArgs<float> a = S.sweep_args<float>(c->s32[cur], c->s32[cur ^ 1], false, nullptr);
+      a.w = faces32(c);
+      launch_sweep2(a, t, c->st);
+      HIPCHK(hipEventRecord(e0, c->st));
+      for (int j = 0; j < sweeps; j += 2) {
+        SweepArgs<float> b = S.sweep_args<float>(c->s32[cur], c->s32[cur ^ 1], false, nullptr);
+        b.w = faces32(c);
+        launch_sweep2(b, t, c->st);
+        cur ^= 1;
+      }
+      HIPCHK(hipEventRecord(e1, c->st));
+      HIPCHK(hipEventSynchronize(e1));
+      HIPCHK(hipGetLastError());
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best2) { best2 = ms; best_zc2 = zc2; }
+    }
+  }
+  best_t.zc2 = best_zc2;
+  best_t.two = c->tiles.two;
   c->tiles = best_t;
   c->tiles_fixed = true;
-  TRY(ensure_partial(c, (long long)NV * sweep_blocks(c->g, c->tiles) + 64));
+  TRY(ensure_partial(c, partial_need(c->g, c->tiles)));
   TRY(leave(c, hip_stream));
-  if (best) { best[0] = 64; best[1] = best_t.ty; best[2] = best_t.zc; }
+  if (best) { best[0] = best_t.ty; best[1] = best_t.zc; best[2] = best_t.zc2; }
   return SOCFV_OK;
 }
 

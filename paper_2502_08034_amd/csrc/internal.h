@@ -97,9 +97,18 @@ struct AdjRefreshArgs {
 struct Tiles {
   int ty;   // threads (rows) along y per block; x is one 64-wide wave
   int zc;   // z cells marched per block
+  int zc2;  // z cells per block of the two-sweep kernel
+  int two;  // FP32 sweeps two per launch where the four-cell path applies
 };
 
 dim3 sweep_grid(const Grid &g, const Tiles &t);
+// FP32 sweeps use four cells per lane when nx % 4 == 0 (grid: 256 x cells per block)
+bool vec4_path(const Grid &g);
+dim3 sweep_grid_v4(const Grid &g, const Tiles &t);
+// two FP32 sweeps per launch (nx even): tiles of 124 x 14 output cells
+bool two_path(const Grid &g);
+dim3 sweep2_grid(const Grid &g, const Tiles &t);
+void launch_sweep2(const SweepArgs<float> &a, const Tiles &t, hipStream_t st);
 
 // ---- kernels (launch wrappers; all enqueue on `st`) ---------------------------------
 

@@ -257,6 +257,33 @@ __device__ __forceinline__ T residual(const Cell<T> &q, T lam, T s_eq) {
   return r;
 }
 
+// The same residual, rearranged for the FP32 sweeps with fewer operations:
+// max(w,0) s_nb - max(-w,0) s_P = max(w,0)(s_nb - s_P) + w s_P for a face with inflow
+// velocity w, so
+//   R_P = sum_f (max(win_f, 0) + G_f)(s_nb(f) - s_P) - s_P div_P + lam (s_eq - s_P),
+//   div_P = sum of outward face velocities.
+// Closed faces have w = 0 and G = 0; the outlet face takes s_nb = s_P.  G_f comes from
+// one byte of closed-face bits (fibre faces, plus the walls and the outlet of this cell).
+__device__ __forceinline__ float gbit(unsigned closed, int k) {
+  return (float)(((~closed) >> k) & 1u);
+}
+
+__device__ __forceinline__ float residual_fast(float c, float xm, float xp, float ym, float yp,
+                                               float zm, float zp, float wxm, float wxp,
+                                               float wym, float wyp, float wzm, float wzp,
+                                               unsigned closed, float gxm_inlet, float lam,
+                                               float s_eq) {
+  const float div = (wxp - wxm) + (wyp - wym) + (wzp - wzm);
+  float r = lam * (s_eq - c) - c * div;
+  r += (fmaxf(wxm, 0.f) + (gbit(closed, 0) + gxm_inlet)) * (xm - c);
+  r += (fmaxf(-wxp, 0.f) + gbit(closed, 1)) * (xp - c);
+  r += (fmaxf(wym, 0.f) + gbit(closed, 2)) * (ym - c);
+  r += (fmaxf(-wyp, 0.f) + gbit(closed, 3)) * (yp - c);
+  r += (fmaxf(wzm, 0.f) + gbit(closed, 4)) * (zm - c);
+  r += (fmaxf(-wzp, 0.f) + gbit(closed, 5)) * (zp - c);
+  return r;
+}
+
 // Reversed-advection (transpose) action at P: (A^T psi)_P for updated cells, with the
 // neighbours' psi (zero on held and fibre cells, which cannot couple):
 //   sum_f (max(w_f,0) + G_f)(psi_P - psi_nb) + outlet w psi_P + lam psi_P,
@@ -367,8 +394,417 @@ __global__ void __launch_bounds__(1024) k_sweep(SweepArgs<T> a) {
   if (RES) block_store<NV>(acc, 0u, a.partial + (long long)NV * (blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)));
 }
 
+// Block order across the eight XCDs: hardware hands consecutive workgroups to the XCDs
+// in turn, so logical tile L is given to workgroup b with L contiguous per XCD.  Tiles that
+// are neighbours in y and z then run on the same XCD and share its L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int x = b & 7, k = b >> 3;
+  return x * q + min(x, r) + k;
+}
+
+// FP32 sweep with four consecutive x cells per lane (16-byte loads and stores); rows of
+// 256 cells per wave.  Used when nx is a multiple of 4.  The x neighbours of a lane's
+// group come from the adjacent lanes by shuffles; the wave's edge lanes load them.
+template <bool DC, bool RES>
+__global__ void __launch_bounds__(1024) k_sweep_v4(SweepArgs<float> a, int gx, int gy, int gz);
+
+// Two sweeps per launch (time skewing along the z march).  A block of 64 x 16 lanes holds
+// a (64 W) x 16 tile, W consecutive x cells per lane, and writes the second sweep on its
+// interior (62 W) x 14 cells; tiles overlap by one lane in x and one row in y on each side,
+// where the first sweep is recomputed.  Marching plane j, the block computes the first
+// sweep s1(j) from s(j-1..j+1) over the whole tile, stages s1(j) in LDS (three plane
+// buffers, one barrier per plane), and the second sweep at plane j-1 from s1(j-2..j): the
+// own column from registers, x and y neighbours from LDS.  State, velocities, flags and
+// the frozen residual come from HBM once for two sweeps.  Each sweep is the arithmetic of
+// one k_sweep_v4 sweep, cell by cell.
+constexpr int T2_ROWS = 16, T2_W = 2, T2_OUT_X = 62 * T2_W, T2_OUT_Y = 14;
+
+template <int W>
+struct VecW {
+  float v[W];
+};
+
+template <int W>
+__device__ __forceinline__ VecW<W> ldw(const float *p) {
+  VecW<W> r;
+  if constexpr (W == 4) {
+    float4 t = *(const float4 *)p;
+    r.v[0] = t.x; r.v[1] = t.y; r.v[2] = t.z; r.v[3] = t.w;
+  } else if constexpr (W == 2) {
+    float2 t = *(const float2 *)p;
+    r.v[0] = t.x; r.v[1] = t.y;
+  } else {
+    r.v[0] = *p;
+  }
+  return r;
+}
+
+template <int W>
+__device__ __forceinline__ void stw(float *p, const VecW<W> &r) {
+  if constexpr (W == 4) *(float4 *)p = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+  else if constexpr (W == 2) *(float2 *)p = make_float2(r.v[0], r.v[1]);
+  else *p = r.v[0];
+}
+
+template <int W>
+__device__ __forceinline__ unsigned ldflags(const uint8_t *p) {
+  if constexpr (W == 4) return *(const unsigned *)p;
+  else if constexpr (W == 2) return *(const unsigned short *)p;
+  else return *p;
+}
+
+template <int W>
+__device__ __forceinline__ VecW<W> zerow() {
+  VecW<W> r;
+#pragma unroll
+  for (int k = 0; k < W; ++k) r.v[k] = 0.f;
+  return r;
+}
+
+template <int W>
+struct CoefW {        // per-lane coefficients of one plane (W cells)
+  VecW<W> wx, wym, wyp, wzl, wzu, r0;
+  float wxr;          // x face velocity after the lane's last cell
+  unsigned fl;
+};
+
+// One explicit FP32 sweep of W cells: out = s + dt (R(s) [+ r0]), rout = the residual used.
+template <bool DC, int W>
+__device__ __forceinline__ void sweepw(const SweepArgs<float> &a, const CoefW<W> &c,
+                                       const VecW<W> &sc, float left, float right,
+                                       const VecW<W> &sdn, const VecW<W> &sup,
+                                       const VecW<W> &sym, const VecW<W> &syp, int x, int y,
+                                       int z, bool up, long long i, VecW<W> &out,
+                                       VecW<W> &rout) {
+  const int nx = a.g.nx, ny = a.g.ny;
+  const bool yl = y > 0, yr = y < ny - 1;
+  // walls of this row / plane as closed-face bits (y, z); the outlet per cell below
+  const unsigned wall = (yl ? 0u : (unsigned)FL_YM) | (yr ? 0u : (unsigned)FL_YP) |
+                        (z > 0 ? 0u : (unsigned)FL_ZM) | (up ? 0u : (unsigned)FL_ZP);
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const unsigned f = (c.fl >> (8 * k)) & 0xffu;
+    const int xk = x + k;
+    const bool outlet = xk == nx - 1;
+    // inlet face: Dirichlet value on the face, G = 2 (closed bit 0 is never set there)
+    const unsigned closed = f | wall | (outlet ? (unsigned)FL_XP : 0u);
+    const float c0 = sc.v[k];
+    const float xm = k == 0 ? left : sc.v[k - 1];
+    const float xp = outlet ? c0 : (k == W - 1 ? right : sc.v[k + 1]);
+    const int nf = __popc(f & FL_FIBRE);
+    const bool held = a.pinned && nf > 0;
+    const float kap = a.kappa ? a.kappa[i + k] : 1.f;
+    float r = residual_fast(c0, xm, xp, sym.v[k], syp.v[k], sdn.v[k], sup.v[k], c.wx.v[k],
+                            k == W - 1 ? c.wxr : c.wx.v[k + 1], c.wym.v[k], c.wyp.v[k],
+                            c.wzl.v[k], c.wzu.v[k], closed, xk == 0 ? 1.f : 0.f,
+                            a.Da * kap * (float)nf, a.s_eq);
+    if (DC) r += c.r0.v[k];
+    const bool pore = f & FL_PORE;
+    if (held || !pore) r = 0.f;
+    float o = held ? (DC ? 0.f : a.s_eq) : c0 + a.dt * r;
+    if (!pore) o = 0.f;
+    out.v[k] = o;
+    rout.v[k] = r;
+  }
+}
+
+// Data a lane needs from plane j for the first sweep there (besides s(j) itself).
+template <int W>
+struct PlaneW {
+  VecW<W> s_up, sym, syp;   // s(j+1) own column, s(j) rows y-1 / y+1
+  CoefW<W> c;               // coefficients of plane j (c.wzl filled by the caller)
+  float left, right;        // s(j) at x-1 and x+W from global (edge lanes only)
+};
+
+template <bool DC, int W>
+__device__ __forceinline__ void load_plane_w(const SweepArgs<float> &a, PlaneW<W> &d, long long i,
+                                             int j, int x, int y, int lane, bool act, bool yl,
+                                             bool yr, bool last) {
+  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const long long pl = (long long)nx * ny;
+  const VecW<W> zw = zerow<W>();
+  d.s_up = d.sym = d.syp = zw;
+  d.c.wx = d.c.wym = d.c.wyp = d.c.wzu = d.c.r0 = zw;
+  d.c.fl = 0u;
+  d.c.wxr = 0.f;
+  d.left = a.s_in;
+  d.right = 0.f;
+  if (act && j < nz) {
+    if (j + 1 < nz) {
+      d.s_up = ldw<W>(a.s + i + pl);
+      d.c.wzu = ldw<W>(a.w.wz + i + pl);
+    }
+    d.c.wx = ldw<W>(a.w.wx + i);
+    d.c.wym = ldw<W>(a.w.wy + i);
+    if (yr) {
+      d.c.wyp = ldw<W>(a.w.wy + i + nx);
+      d.syp = ldw<W>(a.s + i + nx);
+    }
+    if (yl) d.sym = ldw<W>(a.s + i - nx);
+    d.c.fl = ldflags<W>(a.flags + i);
+    if (DC) d.c.r0 = ldw<W>(a.r0 + i);
+    if (x > 0 && lane == 0) d.left = a.s[i - 1];
+    if (last) d.c.wxr = a.w.wxo[y + (long long)ny * j];
+    else if (lane == 63) {
+      d.right = a.s[i + W];
+      d.c.wxr = a.w.wx[i + W];
+    }
+  }
+}
+
+template <bool DC, bool RES>
+__global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int gy, int gz) {
+  constexpr int W = T2_W;
+  __shared__ float lds[2][T2_ROWS][64 * W];
+  const Grid g = a.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int nb = gx * gy * gz;
+  const int L = xcd_tile(blockIdx.x, nb);
+  const int bx = L % gx, by = (L / gx) % gy, bz = L / (gx * gy);
+  const int lane = threadIdx.x, row = threadIdx.y;
+  const int x = bx * T2_OUT_X - W + W * lane;
+  const int y = by * T2_OUT_Y - 1 + row;
+  const int z0 = bz * a.zc;
+  const int z1 = min(z0 + a.zc, nz);
+  const long long pl = (long long)nx * ny;
+  const bool act = x >= 0 && x < nx && y >= 0 && y < ny;
+  const bool outc = act && lane >= 1 && lane <= 62 && row >= 1 && row <= T2_ROWS - 2;
+  const bool yl = y > 0, yr = y < ny - 1;
+  const bool last = x + W >= nx;
+  const VecW<W> zw = zerow<W>();
+  double acc[NV] = {0, 0, 0, 0};
+  const long long ibase = act ? x + (long long)nx * y : 0;
+  // March j over [jb, je]: the first sweep at plane j (j < nz), then the second sweep at
+  // plane j-1 from the LDS copy of s1(j-1) staged in the previous iteration, then stage
+  // s1(j).  Plane j+1's data is fetched one iteration ahead.
+  const int jb = max(z0 - 1, 0);
+  const int je = min(z1, nz);            // inclusive; j == nz only finishes plane nz-1
+  VecW<W> s_dn = zw, s_c = zw, s1_m2 = zw, s1_m1 = zw;
+  CoefW<W> cp;                            // coefficients of plane j-1
+  cp.wx = cp.wym = cp.wyp = cp.wzl = cp.wzu = cp.r0 = zw;
+  cp.wxr = 0.f;
+  cp.fl = 0u;
+  PlaneW<W> nxt;
+  VecW<W> wz_c = zw;
+  if (act) {
+    const long long i0 = ibase + pl * jb;
+    s_c = ldw<W>(a.s + i0);
+    if (jb > 0) s_dn = ldw<W>(a.s + i0 - pl);
+    wz_c = ldw<W>(a.w.wz + i0);
+  }
+  load_plane_w<DC, W>(a, nxt, ibase + pl * jb, jb, x, y, lane, act, yl, yr, last);
+  for (int j = jb; j <= je; ++j) {
+    const long long i = ibase + pl * j;
+    PlaneW<W> cur = nxt;
+    cur.c.wzl = wz_c;
+    if (j + 1 <= je) load_plane_w<DC, W>(a, nxt, i + pl, j + 1, x, y, lane, act, yl, yr, last);
+    const bool have = j < nz;
+    const bool up = j + 1 < nz;
+    // x neighbours of s(j) and the x face velocity after the lane's cells, from the
+    // adjacent lanes (the wave's edge lanes loaded theirs)
+    float left = __shfl_up(s_c.v[W - 1], 1, 64);
+    float right = __shfl_down(s_c.v[0], 1, 64);
+    float wxr = __shfl_down(cur.c.wx.v[0], 1, 64);
+    if (lane == 0 || x == 0) left = cur.left;
+    if (lane == 63 || last) {
+      right = cur.right;
+      wxr = cur.c.wxr;
+    }
+    cur.c.wxr = wxr;
+    VecW<W> s1 = zw, r1;
+    if (act && have)
+      sweepw<DC, W>(a, cur.c, s_c, left, right, s_dn, cur.s_up, cur.sym, cur.syp, x, y, j, up, i,
+                    s1, r1);
+    // second sweep at plane p = j - 1 (interior cells)
+    const int p = j - 1;
+    if (p >= z0 && p < z1 && outc) {
+      const int bp = p & 1;
+      VecW<W> c1, ym1, yp1;
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        c1.v[k] = lds[bp][row][W * lane + k];
+        ym1.v[k] = lds[bp][row - 1][W * lane + k];
+        yp1.v[k] = lds[bp][row + 1][W * lane + k];
+      }
+      const float lft = x == 0 ? a.s_in : lds[bp][row][W * lane - 1];
+      const float rgt = lds[bp][row][W * lane + W];
+      const bool upp = p + 1 < nz;
+      VecW<W> s2, r2;
+      sweepw<DC, W>(a, cp, c1, lft, rgt, s1_m2, upp ? s1 : zw, ym1, yp1, x, y, p, upp, i - pl,
+                    s2, r2);
+      stw<W>(a.s_new + i - pl, s2);
+      if (RES) {
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          const unsigned f = (cp.fl >> (8 * k)) & 0xffu;
+          if (!(f & FL_PORE)) continue;
+          const double rd = (double)r2.v[k];
+          acc[0] += rd * rd;
+          acc[2] += rd;
+          if (!DC) {
+            const double od = (double)s2.v[k];
+            if (!(od >= a.lo && od <= a.hi)) acc[1] += 1.0;
+          } else if (!isfinite(rd)) {
+            acc[1] += 1.0;
+          }
+        }
+      }
+    }
+    // stage s1(j) for the next iteration's second sweep
+#pragma unroll
+    for (int k = 0; k < W; ++k) lds[j & 1][row][W * lane + k] = s1.v[k];
+    __syncthreads();
+    s1_m2 = s1_m1;
+    s1_m1 = s1;
+    s_dn = s_c;
+    s_c = cur.s_up;
+    wz_c = cur.c.wzu;
+    cp = cur.c;
+  }
+  if (RES) block_store<NV>(acc, 0u, a.partial + (long long)NV * blockIdx.x);
+}
+
+template <bool DC, bool RES>
+__global__ void __launch_bounds__(1024) k_sweep_v4(SweepArgs<float> a, int gx, int gy, int gz) {
+  constexpr int W = 4;
+  const Grid g = a.g;
+  const int nx = g.nx, ny = g.ny;
+  const int nb = gx * gy * gz;
+  const int L = xcd_tile(blockIdx.x, nb);
+  const int bx = L % gx, by = (L / gx) % gy, bz = L / (gx * gy);
+  const int lane = threadIdx.x;
+  const int x = bx * 256 + W * lane;
+  const int y = by * blockDim.y + threadIdx.y;
+  const int z0 = bz * a.zc;
+  const int z1 = min(z0 + a.zc, g.nz);
+  const long long pl = (long long)nx * ny;
+  const bool act = x < nx && y < ny;
+  const bool yl = y > 0, yr = y < ny - 1;
+  const bool last = x + W >= nx;          // this group holds the outlet cell
+  double acc[NV] = {0, 0, 0, 0};
+  const VecW<W> zw = zerow<W>();
+  long long i = act ? x + (long long)nx * (y + (long long)ny * z0) : 0;
+  VecW<W> sc = zw, sdn = zw, wzc = zw;
+  if (act) {
+    sc = ldw<W>(a.s + i);
+    if (z0 > 0) sdn = ldw<W>(a.s + i - pl);
+    wzc = ldw<W>(a.w.wz + i);
+  }
+  for (int z = z0; z < z1; ++z, i += pl) {
+    const bool up = z + 1 < g.nz;
+    CoefW<W> cc;
+    cc.wx = cc.wym = cc.wyp = cc.wzu = cc.r0 = zw;
+    cc.wzl = wzc;
+    cc.fl = 0u;
+    VecW<W> sup = zw, sym = zw, syp = zw;
+    if (act) {
+      if (up) {
+        sup = ldw<W>(a.s + i + pl);
+        cc.wzu = ldw<W>(a.w.wz + i + pl);
+      }
+      cc.wx = ldw<W>(a.w.wx + i);
+      cc.wym = ldw<W>(a.w.wy + i);
+      if (yr) {
+        cc.wyp = ldw<W>(a.w.wy + i + nx);
+        syp = ldw<W>(a.s + i + nx);
+      }
+      if (yl) sym = ldw<W>(a.s + i - nx);
+      cc.fl = ldflags<W>(a.flags + i);
+      if (DC) cc.r0 = ldw<W>(a.r0 + i);
+    }
+    // x neighbours: lane-1 holds x-1, lane+1 holds x+4 and the face velocity at x+4
+    float left = __shfl_up(sc.v[W - 1], 1, 64);
+    float right = __shfl_down(sc.v[0], 1, 64);
+    float wxr = __shfl_down(cc.wx.v[0], 1, 64);
+    if (act) {
+      if (x == 0) left = a.s_in;
+      else if (lane == 0) left = a.s[i - 1];
+      if (last) {
+        wxr = a.w.wxo[y + (long long)ny * z];
+        right = 0.f;
+      } else if (lane == 63) {
+        right = a.s[i + W];
+        wxr = a.w.wx[i + W];
+      }
+    }
+    cc.wxr = wxr;
+    if (act) {
+      VecW<W> out, r;
+      sweepw<DC, W>(a, cc, sc, left, right, sdn, sup, sym, syp, x, y, z, up, i, out, r);
+      stw<W>(a.s_new + i, out);
+      if (RES) {
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          const unsigned f = (cc.fl >> (8 * k)) & 0xffu;
+          if (!(f & FL_PORE)) continue;
+          const double rd = (double)r.v[k];
+          acc[0] += rd * rd;
+          acc[2] += rd;
+          if (!DC) {
+            const double od = (double)out.v[k];
+            if (!(od >= a.lo && od <= a.hi)) acc[1] += 1.0;
+          } else if (!isfinite(rd)) {
+            acc[1] += 1.0;
+          }
+        }
+      }
+    }
+    sdn = sc;
+    sc = sup;
+    wzc = cc.wzu;
+  }
+  if (RES) block_store<NV>(acc, 0u, a.partial + (long long)NV * blockIdx.x);
+}
+
+bool vec4_path(const Grid &g) { return (g.nx & 3) == 0; }
+
+bool two_path(const Grid &g) { return (g.nx % T2_W) == 0; }
+
+dim3 sweep2_grid(const Grid &g, const Tiles &t) {
+  return dim3((unsigned)((g.nx + T2_OUT_X - 1) / T2_OUT_X),
+              (unsigned)((g.ny + T2_OUT_Y - 1) / T2_OUT_Y),
+              (unsigned)((g.nz + t.zc2 - 1) / t.zc2));
+}
+
+void launch_sweep2(const SweepArgs<float> &a, const Tiles &t, hipStream_t st) {
+  dim3 gv = sweep2_grid(a.g, t);
+  const unsigned nb = gv.x * gv.y * gv.z;
+  SweepArgs<float> b = a;
+  b.zc = t.zc2;
+  dim3 block(64, T2_ROWS, 1);
+  const bool dc = a.r0 != nullptr, res = a.partial != nullptr;
+  if (dc) {
+    if (res) k_sweep2<true, true><<<nb, block, 0, st>>>(b, gv.x, gv.y, gv.z);
+    else k_sweep2<true, false><<<nb, block, 0, st>>>(b, gv.x, gv.y, gv.z);
+  } else {
+    if (res) k_sweep2<false, true><<<nb, block, 0, st>>>(b, gv.x, gv.y, gv.z);
+    else k_sweep2<false, false><<<nb, block, 0, st>>>(b, gv.x, gv.y, gv.z);
+  }
+}
+
+dim3 sweep_grid_v4(const Grid &g, const Tiles &t) {
+  return dim3((unsigned)((g.nx + 255) / 256), (unsigned)((g.ny + t.ty - 1) / t.ty),
+              (unsigned)((g.nz + t.zc - 1) / t.zc));
+}
+
 template <typename T>
 void launch_sweep(const SweepArgs<T> &a, const Tiles &t, hipStream_t st) {
+  if (sizeof(T) == 4 && vec4_path(a.g)) {
+    const SweepArgs<float> &af = reinterpret_cast<const SweepArgs<float> &>(a);
+    dim3 gv = sweep_grid_v4(a.g, t);
+    const unsigned nb = gv.x * gv.y * gv.z;
+    dim3 block(64, t.ty, 1);
+    const bool dc = a.r0 != nullptr, res = a.partial != nullptr;
+    if (dc) {
+      if (res) k_sweep_v4<true, true><<<nb, block, 0, st>>>(af, gv.x, gv.y, gv.z);
+      else k_sweep_v4<true, false><<<nb, block, 0, st>>>(af, gv.x, gv.y, gv.z);
+    } else {
+      if (res) k_sweep_v4<false, true><<<nb, block, 0, st>>>(af, gv.x, gv.y, gv.z);
+      else k_sweep_v4<false, false><<<nb, block, 0, st>>>(af, gv.x, gv.y, gv.z);
+    }
+    return;
+  }
   dim3 grid = sweep_grid(a.g, t), block(64, t.ty, 1);
   const bool dc = a.r0 != nullptr, res = a.partial != nullptr;
   if (dc) {

@@ -68,7 +68,7 @@ def _load():
         "socfv_solve_soc_adjoint": (i, [P, C.POINTER(Params), P, C.POINTER(d), P,
                                         C.POINTER(Stats), P]),
         "socfv_batch_solve": (i, [i, PP, C.POINTER(Params), PP, C.POINTER(Stats), P]),
-        "socfv_set_tiles": (i, [P, i, i]),
+        "socfv_set_tiles": (i, [P, i, i, i, i]),
         "socfv_autotune": (i, [P, i, C.POINTER(C.c_int), P]),
         "socfv_info": (i, [P, C.POINTER(C.c_int), C.POINTER(C.c_long)]),
         "socfv_destroy": (None, [P]),
@@ -236,8 +236,9 @@ def batch_solve(ctxs, ps, want_states=True):
     return states, list(sts)
 
 
-def set_tiles(ctx: Context, tile_y=0, z_chunk=0):
-    _check(_lib.socfv_set_tiles(ctx.handle, int(tile_y), int(z_chunk)))
+def set_tiles(ctx: Context, tile_y=0, z_chunk=0, z_chunk2=0, two_sweeps=-1):
+    _check(_lib.socfv_set_tiles(ctx.handle, int(tile_y), int(z_chunk), int(z_chunk2),
+                                int(two_sweeps)))
 
 
 def autotune(ctx: Context, sweeps=20):

@@ -43,6 +43,12 @@ CASES = {
     "ragged70x37x29": lambda: fibre_case(70, 37, 29, 3.0, 0.82, 21, 1.0),
     "ragged130x9x65": lambda: fibre_case(130, 9, 65, 2.5, 0.85, 22, 2.0),
     "open40x3x2": lambda: I.plug_flow_case(40, 3, 2, 0.7),
+    # nx % 4 == 0 takes the four-cells-per-lane FP32 sweep; nx = 260 leaves one lane
+    # active in the second 256-cell block row
+    "vec100x37x29": lambda: fibre_case(100, 37, 29, 3.0, 0.82, 24, 1.0),
+    "vec260x11x7": lambda: fibre_case(260, 11, 7, 2.0, 0.85, 25, 1.5),
+    # odd nx: scalar FP32 sweeps only
+    "odd63x21x17": lambda: fibre_case(63, 21, 17, 2.5, 0.85, 26, 1.0),
 }
 
 
@@ -265,3 +271,23 @@ def test_single_cell_and_degenerate(sv):
                                                    s_eq=0.2, Da=0.45))
     expect = ((u + 2) * 1.0 + 0.45 * 0.2) / (u + 2 + 0.45)
     assert abs(float(s[0, 0, 0]) - expect) < 1e-13
+
+
+@pytest.mark.parametrize("shape", [(128, 40, 33), (70, 37, 29), (260, 21, 13), (64, 32, 32)])
+def test_two_sweep_launches_match_single_sweeps(sv, shape):
+    """FP32 sweeps fused two per launch give the same iterates as one sweep per launch."""
+    nx, ny, nz = shape
+    solid, u = fibre_case(nx, ny, nz, 3.0, 0.85, 31, 1.0)
+    pb = make(sv, solid, u)
+    out = {}
+    for two in (0, 1):
+        sv.set_tiles(pb.ctx, 0, 0, 0, two)
+        for prec in ("fp32_plain", "fp32"):
+            p = sv.params(precision=prec, tol=0.0, max_iter=400, check_every=200)
+            s, st = sv.solve_soc_steady(pb.ctx, p)
+            out[(two, prec)] = (s.cpu().numpy(), st.iterations)
+    for prec in ("fp32_plain", "fp32"):
+        a, na = out[(0, prec)]
+        b, nb = out[(1, prec)]
+        assert na == nb
+        assert np.abs(a - b).max() <= 1e-6, (prec, np.abs(a - b).max())
