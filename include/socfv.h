@@ -109,6 +109,7 @@ typedef struct {
   double ms_fp64;     /* GPU time of the FP64 sweeps (excluding refreshes) */
   double ms_refresh;  /* GPU time of the FP64 residual refreshes */
   long sweeps_fp64;   /* FP64 sweeps excluding refreshes */
+  int tile_y, z_chunk; /* launch shape of the sweeps used */
 } socfv_stats;
 
 /* Fill p with defaults: s_in 1, s_eq 0, Da 0.45, FINITE_RATE, FP32, cfl 0.4, tol 1e-8,
@@ -186,11 +187,15 @@ int socfv_solve_soc_adjoint(socfv_ctx *c, const socfv_params *p, double *dU_dkap
                             void *hip_stream);
 
 /*
- * Many problems (contexts with geometry and velocity set) solved together: every
- * FP32 / FP64 sweep is one launch over a tile work list spanning all unfinished problems,
- * and chunks of sweeps are captured once as a hipGraph and replayed.  Each problem
- * stops at its own residual (its own p[i]) and keeps its own dt and tau.  p and st are
- * host arrays of n entries; s_out (host array of n device pointers, nullable entries).
+ * Many problems (contexts with geometry and velocity set; uneven sizes allowed) solved
+ * together.  With every p[i].precision == SOCFV_FP32, each FP32 sweep is one launch over
+ * a tile work list spanning all unfinished problems (persistent blocks, contiguous tile
+ * runs per XCD), chunks of check_every sweeps are captured once as a hipGraph and
+ * replayed, and each problem keeps its own dt, tau, FP64 refreshes and stopping rule
+ * (its own p[i]); the block shape is chosen by timing candidates on the batch.  Other
+ * precisions solve the problems one after another.  p, st: host arrays of n entries;
+ * s_out: host array of n device pointers (nullable, entries nullable).  Returns the worst
+ * status (OK < NOT_CONVERGED) or the first error.
  */
 int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
                       double *const *s_out, socfv_stats *st, void *hip_stream);

@@ -655,6 +655,8 @@ int socfv_solve_soc_steady(socfv_ctx *c, const socfv_params *p, const double *s_
   s.ms_fp64 = S.ms64;
   s.ms_refresh = S.msref;
   s.sweeps_fp64 = S.sw64;
+  s.tile_y = S.t.ty;
+  s.z_chunk = S.t.zc;
   s.dt = S.dt;
   s.tau = S.tau;
   s.residual = p->precision == SOCFV_FP64 ? res : s.residual;
@@ -940,18 +942,268 @@ int socfv_info(const socfv_ctx *c, int dims[3], long counts[3]) {
 
 int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
                       double *const *s_out, socfv_stats *st, void *hip_stream) {
-  // sequential fallback until the batched kernel lands
+  const double t0 = now_s();
   if (n < 0 || (n > 0 && (!ctxs || !p))) return fail(SOCFV_INVALID_ARG, "bad batch arguments");
-  int worst = SOCFV_OK;
+  if (n == 0) return SOCFV_OK;
+  bool batched = true;
   for (int i = 0; i < n; ++i) {
-    socfv_stats s{};
-    int r = socfv_solve_soc_steady(ctxs[i], &p[i], nullptr, s_out ? s_out[i] : nullptr, &s,
-                                   hip_stream);
-    if (st) st[i] = s;
-    if (r < 0) return r;
-    if (r > worst) worst = r;
+    if (!ctxs[i]) return fail(SOCFV_INVALID_ARG, "context %d is NULL", i);
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(SOCFV_INVALID_ARG, "context %d repeated", i);
+    TRY(check_params(&p[i]));
+    if (!ctxs[i]->have_velocity) return fail(SOCFV_INVALID_ARG, "context %d: velocity not set", i);
+    if (p[i].precision != SOCFV_FP32) batched = false;
   }
-  return worst;
+  if (!batched) {
+    // FP64 / plain-FP32 problems: one solve after another
+    int worst = SOCFV_OK;
+    for (int i = 0; i < n; ++i) {
+      socfv_stats s{};
+      int r = socfv_solve_soc_steady(ctxs[i], &p[i], nullptr, s_out ? s_out[i] : nullptr, &s,
+                                     hip_stream);
+      if (st) st[i] = s;
+      if (r < 0) return r;
+      if (r > worst) worst = r;
+    }
+    return worst;
+  }
+  // One library stream for the whole batch (graph capture needs a non-default stream);
+  // the contexts' own streams are swapped for it during the call.
+  hipStream_t bs = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&bs, hipStreamNonBlocking));
+  std::vector<hipStream_t> saved(n);
+  for (int i = 0; i < n; ++i) { saved[i] = ctxs[i]->st; ctxs[i]->st = bs; }
+  BatchProb *d_probs = nullptr;
+  int *d_tiles = nullptr, *d_work = nullptr, *d_nwork = nullptr, *h_work = nullptr;
+  double *d_part = nullptr, *d_out = nullptr, *h_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  auto cleanup = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamSynchronize(bs);
+    hfree(d_probs); hfree(d_tiles); hfree(d_work); hfree(d_nwork); hfree(d_part); hfree(d_out);
+    if (h_work) (void)hipHostFree(h_work);
+    if (h_out) (void)hipHostFree(h_out);
+    for (int i = 0; i < n; ++i) ctxs[i]->st = saved[i];
+    (void)hipStreamDestroy(bs);
+  };
+  int rc = [&]() -> int {
+    TRY(enter(ctxs[0], hip_stream));
+    std::vector<Solver> S;
+    S.reserve(n);
+    std::vector<double> res(n), target(n), best(n, INFINITY);
+    std::vector<int> stall(n, 0), cur(n, 1), status(n, SOCFV_NOT_CONVERGED), done(n, 0);
+    std::vector<double> out(NV);
+    for (int i = 0; i < n; ++i) {
+      S.push_back(Solver{ctxs[i], &p[i]});
+      TRY(S[i].setup());
+      socfv_ctx *c = ctxs[i];
+      launch_init_state(c->g, c->flags, nullptr, p[i].s_in, p[i].s_eq, S[i].pinned, c->s64[0], bs);
+      HIPCHK(hipGetLastError());
+      TRY(S[i].refresh(0, 1, nullptr, out.data()));
+      res[i] = S[i].res_of(out[0]);
+      TRY(S[i].check(out.data(), res[i]));
+      target[i] = std::fmax(0.5 * p[i].tol, 1e-4 * res[i]);
+      launch_fill_f32(c->s32[0], c->g.n, 0.0f, bs);
+      launch_fill_f32(c->s32[1], c->g.n, 0.0f, bs);
+      if (res[i] < p[i].tol) { done[i] = 1; status[i] = SOCFV_OK; }
+    }
+    // tiles: one block shape for the batch, picked by timing a few sweeps per candidate
+    auto build = [&](int ty, int zc, std::vector<BatchProb> &hp, std::vector<int> &tp) {
+      hp.assign(n, BatchProb{});
+      tp.clear();
+      for (int i = 0; i < n; ++i) {
+        socfv_ctx *c = ctxs[i];
+        BatchProb &b = hp[i];
+        b.nx = c->g.nx; b.ny = c->g.ny; b.nz = c->g.nz;
+        b.flags = c->flags;
+        b.wx = c->w32[0]; b.wy = c->w32[1]; b.wz = c->w32[2]; b.wxo = c->w32[3];
+        b.kappa = c->kappa;
+        b.s0 = c->s32[0]; b.s1 = c->s32[1];
+        b.r0 = c->r0;
+        b.dt = (float)S[i].dt; b.Da = (float)p[i].Da; b.s_in = (float)p[i].s_in;
+        b.s_eq = (float)p[i].s_eq; b.lo = S[i].lo; b.hi = S[i].hi; b.pinned = S[i].pinned;
+        b.gx = (c->g.nx + 63) / 64; b.gy = (c->g.ny + ty - 1) / ty;
+        b.zc = std::min(zc, c->g.nz);
+        b.gz = (c->g.nz + b.zc - 1) / b.zc;
+        b.tile0 = (int)tp.size();
+        for (int t = 0; t < b.gx * b.gy * b.gz; ++t) tp.push_back(i);
+      }
+    };
+    int dev = 0, ncu = 256;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    std::vector<BatchProb> hp;
+    std::vector<int> tp;
+    size_t max_tiles = 0;
+    const int tys[] = {2, 4, 8};
+    const int zcs[] = {2, 4, 8, 16};
+    for (int ty : tys)
+      for (int zc : zcs) {
+        build(ty, zc, hp, tp);
+        max_tiles = std::max(max_tiles, tp.size());
+      }
+    HIPCHK(hipMalloc(&d_probs, sizeof(BatchProb) * n));
+    HIPCHK(hipMalloc(&d_tiles, sizeof(int) * max_tiles));
+    HIPCHK(hipMalloc(&d_work, sizeof(int) * max_tiles));
+    HIPCHK(hipMalloc(&d_nwork, sizeof(int)));
+    HIPCHK(hipMalloc(&d_part, sizeof(double) * NV * max_tiles));
+    HIPCHK(hipMalloc(&d_out, sizeof(double) * NV * n));
+    HIPCHK(hipHostMalloc(&h_work, sizeof(int) * (max_tiles + 1), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(&h_out, sizeof(double) * NV * n, hipHostMallocDefault));
+    // work list = every tile of the unfinished problems (count at h_work[0])
+    auto upload_work = [&](const std::vector<BatchProb> &hp_, const std::vector<int> &done_) -> int {
+      int m = 0;
+      for (int i = 0; i < n; ++i) {
+        if (done_[i]) continue;
+        const int nt = hp_[i].gx * hp_[i].gy * hp_[i].gz;
+        for (int t = 0; t < nt; ++t) h_work[1 + m++] = hp_[i].tile0 + t;
+      }
+      h_work[0] = m;
+      HIPCHK(hipMemcpyAsync(d_nwork, h_work, sizeof(int), hipMemcpyHostToDevice, bs));
+      if (m) HIPCHK(hipMemcpyAsync(d_work, h_work + 1, sizeof(int) * m, hipMemcpyHostToDevice, bs));
+      HIPCHK(hipStreamSynchronize(bs));   // h_work is rewritten by the next upload
+      return 0;
+    };
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    int bty = 4, bzc = 8;
+    auto nblocks_for = [&](int ty, size_t ntiles) {
+      // persistent grid: the blocks that fit the chip at once, never more than the tiles
+      long long per_cu = std::max(1, 2048 / (64 * ty));
+      long long nb = std::min<long long>((long long)ncu * per_cu, (long long)ntiles);
+      return (int)std::max<long long>(nb, 1);
+    };
+    for (int ty : tys)
+      for (int zc : zcs) {
+        build(ty, zc, hp, tp);
+        HIPCHK(hipMemcpyAsync(d_probs, hp.data(), sizeof(BatchProb) * n, hipMemcpyHostToDevice, bs));
+        HIPCHK(hipMemcpyAsync(d_tiles, tp.data(), sizeof(int) * tp.size(), hipMemcpyHostToDevice, bs));
+        std::vector<int> none(n, 0);
+        TRY(upload_work(hp, none));
+        const int nb = nblocks_for(ty, tp.size());
+        // timing sweeps change the correction buffers: they are cleared again below
+        launch_batch_sweep(d_probs, d_tiles, d_work, d_nwork, nb, ty, 0, true, nullptr, bs);
+        HIPCHK(hipEventRecord(e0, bs));
+        for (int j = 0; j < 4; ++j)
+          launch_batch_sweep(d_probs, d_tiles, d_work, d_nwork, nb, ty, j & 1, true, nullptr, bs);
+        HIPCHK(hipEventRecord(e1, bs));
+        HIPCHK(hipEventSynchronize(e1));
+        HIPCHK(hipGetLastError());
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) { best_ms = ms; bty = ty; bzc = zc; }
+      }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    build(bty, bzc, hp, tp);
+    const int ntiles = (int)tp.size();
+    const int nb = nblocks_for(bty, tp.size());
+    HIPCHK(hipMemcpyAsync(d_probs, hp.data(), sizeof(BatchProb) * n, hipMemcpyHostToDevice, bs));
+    HIPCHK(hipMemcpyAsync(d_tiles, tp.data(), sizeof(int) * ntiles, hipMemcpyHostToDevice, bs));
+    TRY(upload_work(hp, done));
+    for (int i = 0; i < n; ++i) {
+      launch_fill_f32(ctxs[i]->s32[0], ctxs[i]->g.n, 0.0f, bs);
+      launch_fill_f32(ctxs[i]->s32[1], ctxs[i]->g.n, 0.0f, bs);
+    }
+    // capture one chunk: K sweeps (parity 0, 1, ...), partials on the last, per-problem sums
+    int K = 2;
+    for (int i = 0; i < n; ++i) K = std::max(K, S[i].chunk_len());
+    HIPCHK(hipStreamSynchronize(bs));
+    HIPCHK(hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal));
+    for (int j = 0; j < K; ++j)
+      launch_batch_sweep(d_probs, d_tiles, d_work, d_nwork, nb, bty, j & 1, true,
+                         j == K - 1 ? d_part : nullptr, bs);
+    launch_batch_reduce(d_probs, n, d_part, d_out, bs);
+    HIPCHK(hipStreamEndCapture(bs, &graph));
+    HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    std::vector<long> it(n, 0);
+    bool changed = false;
+    for (;;) {
+      int nact = 0;
+      for (int i = 0; i < n; ++i) nact += !done[i];
+      if (!nact) break;
+      if (changed) {
+        TRY(upload_work(hp, done));
+        changed = false;
+      }
+      HIPCHK(hipGraphLaunch(exec, bs));
+      HIPCHK(hipMemcpyAsync(h_out, d_out, sizeof(double) * NV * n, hipMemcpyDeviceToHost, bs));
+      HIPCHK(hipStreamSynchronize(bs));
+      for (int i = 0; i < n; ++i) {
+        if (done[i]) continue;
+        S[i].it += K;
+        S[i].it32 += K;
+        const double ri = S[i].res_of(h_out[NV * i]);
+        if (!std::isfinite(ri) || h_out[NV * i + 1] > 0)
+          return fail(SOCFV_DIVERGED, "batch problem %d diverged at sweep %ld", i, S[i].it);
+        bool refresh = ri < target[i] || S[i].it >= p[i].max_iter;
+        if (!refresh) {
+          if (ri < 0.999 * best[i]) { best[i] = ri; stall[i] = 0; }
+          else if (++stall[i] >= 8) refresh = true;
+        }
+        if (!refresh) continue;
+        TRY(S[i].refresh(cur[i], cur[i] ^ 1, ctxs[i]->s32[0], out.data()));
+        cur[i] ^= 1;
+        ++S[i].cycles;
+        res[i] = S[i].res_of(out[0]);
+        TRY(S[i].check(out.data(), res[i]));
+        best[i] = INFINITY;
+        stall[i] = 0;
+        if (res[i] < p[i].tol) {
+          done[i] = 1;
+          status[i] = SOCFV_OK;
+          changed = true;
+        } else if (S[i].it >= p[i].max_iter) {
+          done[i] = 1;
+          changed = true;
+        } else {
+          target[i] = std::fmax(0.5 * p[i].tol, 1e-4 * res[i]);
+          launch_fill_f32(ctxs[i]->s32[0], ctxs[i]->g.n, 0.0f, bs);
+          launch_fill_f32(ctxs[i]->s32[1], ctxs[i]->g.n, 0.0f, bs);
+        }
+      }
+    }
+    // FP64 polish, outputs and states per problem
+    for (int i = 0; i < n; ++i) {
+      socfv_ctx *c = ctxs[i];
+      long np = p[i].polish_iters > 0 ? p[i].polish_iters : S[i].chunk_len();
+      np += np & 1;
+      double pres = res[i];
+      int pc = cur[i];
+      TRY(S[i].run_fp64(pc, pres, np));
+      cur[i] = pc;
+      res[i] = pres;
+      status[i] = pres < p[i].tol ? SOCFV_OK : SOCFV_NOT_CONVERGED;
+      c->have_state = true;
+      c->state_buf = pc;
+      c->last_p = p[i];
+      socfv_stats s{};
+      TRY(eval_outputs(c, &p[i], c->s64[pc], &s));
+      if (s_out && s_out[i])
+        HIPCHK(hipMemcpyAsync(s_out[i], c->s64[pc], sizeof(double) * (size_t)c->g.n,
+                              hipMemcpyDeviceToDevice, bs));
+      s.iterations = S[i].it; s.it_fp32 = S[i].it32; s.it_fp64 = S[i].it64;
+      s.cycles = S[i].cycles; s.status = status[i]; s.dt = S[i].dt; s.tau = S[i].tau;
+      s.ms_fp64 = S[i].ms64; s.ms_refresh = S[i].msref; s.sweeps_fp64 = S[i].sw64;
+      s.tile_y = bty; s.z_chunk = bzc;
+      if (st) st[i] = s;
+    }
+    TRY(leave(ctxs[0], hip_stream));
+    const double el = now_s() - t0;
+    int worst = SOCFV_OK;
+    for (int i = 0; i < n; ++i) {
+      if (st) st[i].seconds = el;
+      worst = std::max(worst, status[i]);
+    }
+    if (worst == SOCFV_NOT_CONVERGED) fail(worst, "some batch problems did not converge");
+    return worst;
+  }();
+  cleanup();
+  return rc;
 }
 
 }  // extern "C"

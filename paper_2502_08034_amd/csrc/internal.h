@@ -93,6 +93,28 @@ struct AdjRefreshArgs {
   int zc;
 };
 
+// One problem of a batched launch (device table entry).
+struct BatchProb {
+  int nx, ny, nz;
+  const uint8_t *flags;
+  const float *wx, *wy, *wz, *wxo;
+  const float *kappa;
+  float *s0, *s1;       // ping-pong buffers: parity 0 reads s0, writes s1
+  const float *r0;      // correction form: frozen FP64 residual (else unused)
+  float dt, Da, s_in, s_eq;
+  double lo, hi;
+  int pinned;
+  int gx, gy, gz, zc;   // tile grid of this problem (64 x ty lanes, zc planes)
+  int tile0;            // index of its first tile in the work list
+};
+
+// work: tile numbers of the unfinished problems; *nwork (device) their count
+void launch_batch_sweep(const BatchProb *probs, const int *tile_prob, const int *work,
+                        const int *nwork, int nblocks, int ty, int parity, bool dc,
+                        double *partial, hipStream_t st);
+void launch_batch_reduce(const BatchProb *probs, int n, const double *partial, double *out,
+                         hipStream_t st);
+
 // Launch shapes.
 struct Tiles {
   int ty;   // threads (rows) along y per block; x is one 64-wide wave

@@ -819,6 +819,144 @@ template void launch_sweep<float>(const SweepArgs<float> &, const Tiles &, hipSt
 template void launch_sweep<double>(const SweepArgs<double> &, const Tiles &, hipStream_t);
 
 // ------------------------------------------------------------------------------------
+// Batched sweeps: many problems of uneven size in one launch
+// ------------------------------------------------------------------------------------
+
+// One launch sweeps every unfinished problem once.  The tiles of all problems are numbered
+// (each tile: 64 x ty lanes, one cell per lane, zc cells along z); the work list holds
+// the tiles of the unfinished problems, and a fixed set of persistent blocks splits it
+// into contiguous runs, placed XCD by XCD so that neighbouring tiles share an L2.
+// Finished problems are not swept, so their buffers keep their parity.  With RES the
+// residual partials are written per tile; k_batch_reduce sums each problem's tiles in a
+// fixed order.
+template <bool DC, bool RES>
+__global__ void __launch_bounds__(1024) k_batch_sweep(const BatchProb *__restrict__ probs,
+                                                     const int *__restrict__ tile_prob,
+                                                     const int *__restrict__ work,
+                                                     const int *__restrict__ nwork, int parity,
+                                                     double *__restrict__ partial) {
+  // the work list holds the tiles of the unfinished problems; its length lives in device
+  // memory so that a captured graph keeps working as problems finish
+  const int nw = *nwork;
+  const int per = (nw + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int w0 = b * per;
+  const int w1 = min(w0 + per, nw);
+  const int lane = threadIdx.x, row = threadIdx.y;
+  for (int w = w0; w < w1; ++w) {
+    const int t = work[w];
+    const int pi = tile_prob[t];
+    const BatchProb &q = probs[pi];
+    double acc[NV] = {0, 0, 0, 0};
+    {
+      const int nx = q.nx, ny = q.ny, nz = q.nz;
+      const long long pl = (long long)nx * ny;
+      const int lt = t - q.tile0;
+      const int bx = lt % q.gx, by = (lt / q.gx) % q.gy, bz = lt / (q.gx * q.gy);
+      const int x = bx * 64 + lane;
+      const int y = by * blockDim.y + row;
+      const int z0 = bz * q.zc;
+      const int z1 = min(z0 + q.zc, nz);
+      const float *s = parity ? q.s1 : q.s0;
+      float *s_new = parity ? q.s0 : q.s1;
+      if (x < nx && y < ny) {
+        const bool xl = x > 0, xr = x < nx - 1, yl = y > 0, yr = y < ny - 1;
+        const float xm_bc = DC ? 0.f : q.s_in;
+        long long i = x + (long long)nx * (y + (long long)ny * z0);
+        float s_c = s[i];
+        float s_dn = z0 > 0 ? s[i - pl] : 0.f;
+        float wz_c = q.wz[i];
+        const unsigned ywall = (yl ? 0u : (unsigned)FL_YM) | (yr ? 0u : (unsigned)FL_YP) |
+                               (xr ? 0u : (unsigned)FL_XP);
+        for (int z = z0; z < z1; ++z, i += pl) {
+          const bool up = z + 1 < nz;
+          const float s_up = up ? s[i + pl] : 0.f;
+          const float wz_u = up ? q.wz[i + pl] : 0.f;
+          const unsigned f = q.flags[i];
+          float out = 0.f;
+          if (f & FL_PORE) {
+            const unsigned closed = f | ywall | (z > 0 ? 0u : (unsigned)FL_ZM) |
+                                    (up ? 0u : (unsigned)FL_ZP);
+            const float xm = xl ? s[i - 1] : xm_bc;
+            const float xp = xr ? s[i + 1] : s_c;
+            const float ym = yl ? s[i - nx] : 0.f;
+            const float yp = yr ? s[i + nx] : 0.f;
+            const float wxm = q.wx[i];
+            const float wxp = xr ? q.wx[i + 1] : q.wxo[y + (long long)ny * z];
+            const float wym = q.wy[i];
+            const float wyp = yr ? q.wy[i + nx] : 0.f;
+            const int nf = __popc(f & FL_FIBRE);
+            const bool held = q.pinned && nf > 0;
+            const float kap = q.kappa ? q.kappa[i] : 1.f;
+            float r = residual_fast(s_c, xm, xp, ym, yp, s_dn, s_up, wxm, wxp, wym, wyp, wz_c, wz_u,
+                                    closed, xl ? 0.f : 1.f, q.Da * kap * (float)nf,
+                                    DC ? 0.f : q.s_eq);
+            if (DC) r += q.r0[i];
+            if (held) r = 0.f;
+            out = held ? (DC ? 0.f : q.s_eq) : s_c + q.dt * r;
+            if (RES) {
+              const double rd = (double)r;
+              acc[0] += rd * rd;
+              acc[2] += rd;
+              if (!DC) {
+                const double od = (double)out;
+                if (!(od >= q.lo && od <= q.hi)) acc[1] += 1.0;
+              } else if (!isfinite(rd)) {
+                acc[1] += 1.0;
+              }
+            }
+          }
+          s_new[i] = out;
+          s_dn = s_c;
+          s_c = s_up;
+          wz_c = wz_u;
+        }
+      }
+    }
+    if (RES) block_store<NV>(acc, 0u, partial + (long long)NV * t);
+  }
+}
+
+// out[p * NV + k] = sum over problem p's tiles of partial[tile * NV + k], fixed order
+__global__ void __launch_bounds__(256) k_batch_reduce(const BatchProb *__restrict__ probs,
+                                                     const double *__restrict__ partial,
+                                                     double *__restrict__ out) {
+  __shared__ double sh[256];
+  const BatchProb &q = probs[blockIdx.x];
+  const int ntile = q.gx * q.gy * q.gz;
+  for (int k = 0; k < NV; ++k) {
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < ntile; j += 256) acc += partial[(long long)NV * (q.tile0 + j) + k];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(long long)NV * blockIdx.x + k] = sh[0];
+    __syncthreads();
+  }
+}
+
+void launch_batch_sweep(const BatchProb *probs, const int *tile_prob, const int *work,
+                        const int *nwork, int nblocks, int ty, int parity, bool dc,
+                        double *partial, hipStream_t st) {
+  dim3 block(64, ty, 1);
+  if (dc) {
+    if (partial) k_batch_sweep<true, true><<<nblocks, block, 0, st>>>(probs, tile_prob, work, nwork, parity, partial);
+    else k_batch_sweep<true, false><<<nblocks, block, 0, st>>>(probs, tile_prob, work, nwork, parity, partial);
+  } else {
+    if (partial) k_batch_sweep<false, true><<<nblocks, block, 0, st>>>(probs, tile_prob, work, nwork, parity, partial);
+    else k_batch_sweep<false, false><<<nblocks, block, 0, st>>>(probs, tile_prob, work, nwork, parity, partial);
+  }
+}
+
+void launch_batch_reduce(const BatchProb *probs, int n, const double *partial, double *out,
+                         hipStream_t st) {
+  k_batch_reduce<<<n, 256, 0, st>>>(probs, partial, out);
+}
+
+// ------------------------------------------------------------------------------------
 // FP64 refresh of the defect correction: t = s64 + delta, r0 = R64(t)
 // ------------------------------------------------------------------------------------
 

@@ -71,16 +71,18 @@ def _x_range(nx: int, r: float):
     return lo, hi
 
 
-def _cyl_mask(nx, ny, nz, axis, x0, c0, r):
-    """Voxels of a cylinder along y (c0 = z centre) or z (c0 = y centre)."""
-    xs = np.arange(nx) + 0.5
+def _cyl_window(nx, ny, nz, axis, x0, c0, r):
+    """Voxels of a cylinder along y (c0 = z centre) or z (c0 = y centre), returned as a
+    window of the box (index slices) and the boolean mask inside it."""
+    n_c = nz if axis == "y" else ny
+    xa, xb = max(0, int(math.floor(x0 - r - 0.5))), min(nx, int(math.ceil(x0 + r + 0.5)) + 1)
+    ca, cb = max(0, int(math.floor(c0 - r - 0.5))), min(n_c, int(math.ceil(c0 + r + 0.5)) + 1)
+    xs = np.arange(xa, xb) + 0.5
+    cs = np.arange(ca, cb) + 0.5
+    m2 = (xs[None, :] - x0) ** 2 + (cs[:, None] - c0) ** 2 < r * r     # (c, x)
     if axis == "y":
-        zs = np.arange(nz) + 0.5
-        d2 = (xs[None, :] - x0) ** 2 + (zs[:, None] - c0) ** 2      # (nz, nx)
-        return np.broadcast_to((d2 < r * r)[:, None, :], (nz, ny, nx))
-    ys = np.arange(ny) + 0.5
-    d2 = (xs[None, :] - x0) ** 2 + (ys[:, None] - c0) ** 2          # (ny, nx)
-    return np.broadcast_to((d2 < r * r)[None, :, :], (nz, ny, nx))
+        return (slice(ca, cb), slice(None), slice(xa, xb)), m2[:, None, :]
+    return (slice(None), slice(ca, cb), slice(xa, xb)), m2[None, :, :]
 
 
 def fibres_nonoverlap(nx, ny, nz, radius, porosity, seed, max_tries=200000,
@@ -99,11 +101,13 @@ def fibres_nonoverlap(nx, ny, nz, radius, porosity, seed, max_tries=200000,
         axis = "y" if rng.random() < 0.5 else "z"
         x0 = rng.uniform(lo, hi)
         c0 = rng.uniform(0.0, nz if axis == "y" else ny)
-        m = _cyl_mask(nx, ny, nz, axis, x0, c0, radius)
-        if np.any(solid & m):
+        win, m = _cyl_window(nx, ny, nz, axis, x0, c0, radius)
+        sub = solid[win]
+        m = np.broadcast_to(m, sub.shape)
+        if np.any(sub & m):
             continue
-        solid |= m
-        n_solid = int(np.count_nonzero(solid))
+        sub |= m
+        n_solid += int(np.count_nonzero(m))
         n_fib += 1
     geo = Geometry(solid.astype(np.uint8), radius, n_fib, 0.0,
                    info={"kind": "nonoverlap", "seed": seed, "target_porosity": porosity})

@@ -38,7 +38,7 @@ class Stats(C.Structure):
                 ("flux_out", C.c_double), ("reaction", C.c_double), ("sum_R", C.c_double),
                 ("q_out", C.c_double), ("seconds", C.c_double), ("ms_fp32", C.c_double),
                 ("ms_fp64", C.c_double), ("ms_refresh", C.c_double),
-                ("sweeps_fp64", C.c_long)]
+                ("sweeps_fp64", C.c_long), ("tile_y", C.c_int), ("z_chunk", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
