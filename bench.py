@@ -127,6 +127,23 @@ def accuracy_legs(sv):
     return out
 
 
+def counter_traffic(kernel_tag="k_sweep_v4"):
+    """HBM bytes per launch of the dominant kernel from the committed counter summary, or
+    None when the kernel source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_slab1024_pmc.md")
+    src = os.path.join(ROOT, "paper_2502_08034_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if f"sha256 at measurement: {digest}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("| traffic per launch |"):
+            return float(line.split("|")[2].split("GB")[0]) * 1e9
+    return None
+
+
 def cpu_baseline(geo, u_np, seconds):
     import oracle
     ux, uy, uz = u_np
@@ -264,7 +281,8 @@ def main():
                    "cells": ncell, "pore_cells": info["pore"], "precision": "fp32+fp64",
                    "tiles": list(tiles) if tiles else None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": counter_traffic() if (nx, ny, nz) == (1024, 512, 256) else None,
                      "kernel": "k_sweep_v4<correction> (FP32 correction sweep, one per launch)",
                      "bytes_per_cell_update": BYTES_FP32_DC, "avg_sweep_ms": avg32,
                      "sweeps_timed": n32},
