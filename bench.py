@@ -127,7 +127,7 @@ def accuracy_legs(sv):
     return out
 
 
-def counter_traffic(kernel_tag="k_sweep_v4"):
+def counter_traffic(kernel_tag="k_sweep2"):
     """HBM bytes per launch of the dominant kernel from the committed counter summary, or
     None when the kernel source has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"{kernel_tag}_slab1024_pmc.md")
@@ -262,6 +262,8 @@ def main():
     ms64 = sum(st.ms_fp64 for r in runs for _, st in r)
     n64 = sum(st.sweeps_fp64 for r in runs for _, st in r)
     avg32 = ms32 / n32 if n32 else float("nan")
+    # per cell update 25 B; a launch of the dominant kernel performs two updates of every cell
+    # in 2 x avg32, so achieved = 2 x 25 B x n / (2 x avg32)
     achieved = BYTES_FP32_DC * ncell / (avg32 / 1e3) / 1e9 if n32 else 0.0
     last = {f"{pe:g}": {"U": st.U, "sweeps": st.iterations, "residual": st.residual,
                         "seconds": st.seconds, "balance_rel": abs(st.flux_in - st.flux_out
@@ -283,7 +285,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": counter_traffic() if (nx, ny, nz) == (1024, 512, 256) else None,
-                     "kernel": "k_sweep_v4<correction> (FP32 correction sweep, one per launch)",
+                     "kernel": "k_sweep2<correction> (FP32 correction sweeps, two per launch)",
+                     "bytes_per_launch": 2 * BYTES_FP32_DC * ncell,
                      "bytes_per_cell_update": BYTES_FP32_DC, "avg_sweep_ms": avg32,
                      "sweeps_timed": n32},
         "fp64_sweep": {"avg_ms": ms64 / n64 if n64 else None,

@@ -202,8 +202,8 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
 
 /*
  * Launch shapes.  Single sweeps work on (64 x tile_y) lanes marching z_chunk cells along z;
- * with two_sweeps set, FP32 sweeps on grids with even nx run two sweeps per launch on
- * 64 x 16 lanes marching z_chunk2 cells (off by default).  socfv_set_tiles overrides them for a
+ * with two_sweeps set (the default), FP32 sweeps on grids with even nx run two sweeps per
+ * launch on 64 x 16 lanes marching z_chunk2 cells.  socfv_set_tiles overrides them for a
  * context (0 = keep, two_sweeps < 0 = keep); socfv_autotune times candidate shapes on this
  * context's problem (`sweeps` sweeps each) and keeps the fastest; best[3] (host, nullable)
  * receives tile_y, z_chunk, z_chunk2.

@@ -78,7 +78,7 @@ struct socfv_ctx {
   long npore = 0, nreact = 0, ninlet = 0, noutlet = 0;
   bool have_velocity = false;
   double Q_in = 0, div_max = 0, u_max = 0;
-  Tiles tiles{4, 8, 32, 0};
+  Tiles tiles{4, 8, 32, 1};
   bool tiles_fixed = false;
   // last forward solution
   bool have_state = false;
@@ -99,11 +99,11 @@ Tiles auto_tiles(const Grid &g, int ty) {
   if (zc > g.nz) zc = g.nz;
   // two-sweep kernel: enough blocks to fill the chip, long z marches (2 extra planes each)
   long long t2 = (long long)((g.nx + 123) / 124) * ((g.ny + 13) / 14);
-  long long zc2 = t2 > 0 ? (long long)g.nz * t2 / 1024 : g.nz;
+  long long zc2 = t2 > 0 ? (long long)g.nz * t2 / 2048 : g.nz;
   if (zc2 < 8) zc2 = 8;
-  if (zc2 > 64) zc2 = 64;
+  if (zc2 > 32) zc2 = 32;
   if (zc2 > g.nz) zc2 = g.nz;
-  return Tiles{ty, (int)zc, (int)zc2, 0};
+  return Tiles{ty, (int)zc, (int)zc2, 1};
 }
 
 long long sweep_blocks(const Grid &g, const Tiles &t) {

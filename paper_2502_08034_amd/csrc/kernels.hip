@@ -509,47 +509,52 @@ __device__ __forceinline__ void sweepw(const SweepArgs<float> &a, const CoefW<W>
   }
 }
 
-// Data a lane needs from plane j for the first sweep there (besides s(j) itself).
-template <int W>
-struct PlaneW {
-  VecW<W> s_up, sym, syp;   // s(j+1) own column, s(j) rows y-1 / y+1
-  CoefW<W> c;               // coefficients of plane j (c.wzl filled by the caller)
-  float left, right;        // s(j) at x-1 and x+W from global (edge lanes only)
+// Everything a lane (two cells) reads from plane j: the state one plane up, the state of
+// rows y-1 / y+1, the coefficients, and the x-edge values its wave's edge lanes need.
+struct Plane2 {
+  VecW<2> s_up, sym, syp;
+  CoefW<2> c;
+  float left, right;
 };
 
-template <bool DC, int W>
-__device__ __forceinline__ void load_plane_w(const SweepArgs<float> &a, PlaneW<W> &d, long long i,
-                                             int j, int x, int y, int lane, bool act, bool yl,
-                                             bool yr, bool last) {
+// Loads at clamped 32-bit offsets (every address valid; out-of-range planes, rows and
+// lanes read a copy of a valid cell and their results meet only zero-coefficient faces),
+// then selects for the wall velocities that must be zero.
+template <bool DC>
+__device__ __forceinline__ void load_plane2(const SweepArgs<float> &a, Plane2 &d, unsigned ib,
+                                            unsigned pl, int j, int xc, int yc, int lane,
+                                            bool last, bool yl, bool yr) {
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-  const long long pl = (long long)nx * ny;
-  const VecW<W> zw = zerow<W>();
-  d.s_up = d.sym = d.syp = zw;
-  d.c.wx = d.c.wym = d.c.wyp = d.c.wzu = d.c.r0 = zw;
-  d.c.fl = 0u;
-  d.c.wxr = 0.f;
+  const int jj = min(j, nz - 1);
+  const bool up = jj + 1 < nz;
+  const unsigned o = ib + pl * (unsigned)jj;
+  const unsigned oup = o + (up ? pl : 0u);
+  const unsigned oyp = o + (yr ? (unsigned)nx : 0u);
+  const unsigned oym = o - (yl ? (unsigned)nx : 0u);
+  d.s_up = ldw<2>(a.s + oup);
+  d.sym = ldw<2>(a.s + oym);
+  d.syp = ldw<2>(a.s + oyp);
+  d.c.wx = ldw<2>(a.w.wx + o);
+  d.c.wym = ldw<2>(a.w.wy + o);
+  const VecW<2> wyp = ldw<2>(a.w.wy + oyp);
+  d.c.wzl = ldw<2>(a.w.wz + o);
+  const VecW<2> wzu = ldw<2>(a.w.wz + oup);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    d.c.wyp.v[k] = yr ? wyp.v[k] : 0.f;
+    d.c.wzu.v[k] = up ? wzu.v[k] : 0.f;
+  }
+  d.c.fl = ldflags<2>(a.flags + o);
+  if (DC) d.c.r0 = ldw<2>(a.r0 + o);
+  else d.c.r0 = zerow<2>();
   d.left = a.s_in;
   d.right = 0.f;
-  if (act && j < nz) {
-    if (j + 1 < nz) {
-      d.s_up = ldw<W>(a.s + i + pl);
-      d.c.wzu = ldw<W>(a.w.wz + i + pl);
-    }
-    d.c.wx = ldw<W>(a.w.wx + i);
-    d.c.wym = ldw<W>(a.w.wy + i);
-    if (yr) {
-      d.c.wyp = ldw<W>(a.w.wy + i + nx);
-      d.syp = ldw<W>(a.s + i + nx);
-    }
-    if (yl) d.sym = ldw<W>(a.s + i - nx);
-    d.c.fl = ldflags<W>(a.flags + i);
-    if (DC) d.c.r0 = ldw<W>(a.r0 + i);
-    if (x > 0 && lane == 0) d.left = a.s[i - 1];
-    if (last) d.c.wxr = a.w.wxo[y + (long long)ny * j];
-    else if (lane == 63) {
-      d.right = a.s[i + W];
-      d.c.wxr = a.w.wx[i + W];
-    }
+  d.c.wxr = 0.f;
+  if (lane == 0 && xc > 0) d.left = a.s[o - 1];
+  if (last) d.c.wxr = a.w.wxo[yc + (unsigned)ny * (unsigned)jj];
+  else if (lane == 63) {
+    d.right = a.s[o + 2];
+    d.c.wxr = a.w.wx[o + 2];
   }
 }
 
@@ -567,56 +572,58 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
   const int y = by * T2_OUT_Y - 1 + row;
   const int z0 = bz * a.zc;
   const int z1 = min(z0 + a.zc, nz);
-  const long long pl = (long long)nx * ny;
   const bool act = x >= 0 && x < nx && y >= 0 && y < ny;
   const bool outc = act && lane >= 1 && lane <= 62 && row >= 1 && row <= T2_ROWS - 2;
-  const bool yl = y > 0, yr = y < ny - 1;
-  const bool last = x + W >= nx;
+  const int xc = min(max(x, 0), nx - W);
+  const int yc = min(max(y, 0), ny - 1);
+  const bool yl = yc > 0, yr = yc < ny - 1;
+  const bool last = xc + W >= nx;
+  const unsigned pl = (unsigned)nx * (unsigned)ny;
+  const unsigned ib = (unsigned)xc + (unsigned)nx * (unsigned)yc;
   const VecW<W> zw = zerow<W>();
   double acc[NV] = {0, 0, 0, 0};
-  const long long ibase = act ? x + (long long)nx * y : 0;
-  // March j over [jb, je]: the first sweep at plane j (j < nz), then the second sweep at
-  // plane j-1 from the LDS copy of s1(j-1) staged in the previous iteration, then stage
-  // s1(j).  Plane j+1's data is fetched one iteration ahead.
+  // March j over [jb, je]: first sweep at plane j, second sweep at plane j-1 from the LDS
+  // copy of s1(j-1) staged in the previous step, stage s1(j).  Plane data sit in a ring of
+  // four (j+1 is fetched while j is swept; j-1 feeds the second sweep; j-2 holds s(j-1))
+  // and first-sweep results in a ring of four; the loop is unrolled by four so every ring
+  // index is a compile-time constant.
   const int jb = max(z0 - 1, 0);
   const int je = min(z1, nz);            // inclusive; j == nz only finishes plane nz-1
-  VecW<W> s_dn = zw, s_c = zw, s1_m2 = zw, s1_m1 = zw;
-  CoefW<W> cp;                            // coefficients of plane j-1
-  cp.wx = cp.wym = cp.wyp = cp.wzl = cp.wzu = cp.r0 = zw;
-  cp.wxr = 0.f;
-  cp.fl = 0u;
-  PlaneW<W> nxt;
-  VecW<W> wz_c = zw;
-  if (act) {
-    const long long i0 = ibase + pl * jb;
-    s_c = ldw<W>(a.s + i0);
-    if (jb > 0) s_dn = ldw<W>(a.s + i0 - pl);
-    wz_c = ldw<W>(a.w.wz + i0);
+  Plane2 P[4];
+  VecW<W> S1[4];
+  S1[0] = S1[1] = S1[2] = S1[3] = zw;
+  {
+    const unsigned o = ib + pl * (unsigned)jb;
+    P[2].s_up = jb > 0 ? ldw<W>(a.s + o - pl) : zw;     // s(jb-1)
+    P[3].s_up = ldw<W>(a.s + o);                        // s(jb)
+    P[3].c.wx = P[3].c.wym = P[3].c.wyp = P[3].c.wzl = P[3].c.wzu = P[3].c.r0 = zw;
+    P[3].c.fl = 0u;
+    P[3].c.wxr = 0.f;
+    load_plane2<DC>(a, P[0], ib, pl, jb, xc, yc, lane, last, yl, yr);
   }
-  load_plane_w<DC, W>(a, nxt, ibase + pl * jb, jb, x, y, lane, act, yl, yr, last);
-  for (int j = jb; j <= je; ++j) {
-    const long long i = ibase + pl * j;
-    PlaneW<W> cur = nxt;
-    cur.c.wzl = wz_c;
-    if (j + 1 <= je) load_plane_w<DC, W>(a, nxt, i + pl, j + 1, x, y, lane, act, yl, yr, last);
-    const bool have = j < nz;
-    const bool up = j + 1 < nz;
-    // x neighbours of s(j) and the x face velocity after the lane's cells, from the
-    // adjacent lanes (the wave's edge lanes loaded theirs)
+  auto step = [&](Plane2 &cur, const Plane2 &prev, const Plane2 &pprev, Plane2 &nxt,
+                  VecW<W> &s1_j, const VecW<W> &s1_jm2, int j) {
+    load_plane2<DC>(a, nxt, ib, pl, j + 1, xc, yc, lane, last, yl, yr);
+    const VecW<W> &s_c = prev.s_up;      // s(j)
     float left = __shfl_up(s_c.v[W - 1], 1, 64);
     float right = __shfl_down(s_c.v[0], 1, 64);
     float wxr = __shfl_down(cur.c.wx.v[0], 1, 64);
-    if (lane == 0 || x == 0) left = cur.left;
+    if (lane == 0) left = cur.left;
     if (lane == 63 || last) {
       right = cur.right;
       wxr = cur.c.wxr;
     }
+    if (x == 0) left = a.s_in;
+    // the resolved face velocity stays with the plane: the second sweep reads it next step
     cur.c.wxr = wxr;
-    VecW<W> s1 = zw, r1;
-    if (act && have)
-      sweepw<DC, W>(a, cur.c, s_c, left, right, s_dn, cur.s_up, cur.sym, cur.syp, x, y, j, up, i,
-                    s1, r1);
-    // second sweep at plane p = j - 1 (interior cells)
+    VecW<W> r1;
+    if (j < nz) {
+      sweepw<DC, W>(a, cur.c, s_c, left, right, pprev.s_up, cur.s_up, cur.sym, cur.syp, xc, yc,
+                    j, j + 1 < nz, ib + pl * (unsigned)j, s1_j, r1);
+    } else {
+      s1_j = zw;
+    }
+    // second sweep at plane p = j - 1 on the interior
     const int p = j - 1;
     if (p >= z0 && p < z1 && outc) {
       const int bp = p & 1;
@@ -630,14 +637,15 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
       const float lft = x == 0 ? a.s_in : lds[bp][row][W * lane - 1];
       const float rgt = lds[bp][row][W * lane + W];
       const bool upp = p + 1 < nz;
+      const unsigned ip = ib + pl * (unsigned)p;
       VecW<W> s2, r2;
-      sweepw<DC, W>(a, cp, c1, lft, rgt, s1_m2, upp ? s1 : zw, ym1, yp1, x, y, p, upp, i - pl,
-                    s2, r2);
-      stw<W>(a.s_new + i - pl, s2);
+      sweepw<DC, W>(a, prev.c, c1, lft, rgt, s1_jm2, upp ? s1_j : zw, ym1, yp1, x, y, p, upp,
+                    ip, s2, r2);
+      stw<W>(a.s_new + ip, s2);
       if (RES) {
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-          const unsigned f = (cp.fl >> (8 * k)) & 0xffu;
+          const unsigned f = (prev.c.fl >> (8 * k)) & 0xffu;
           if (!(f & FL_PORE)) continue;
           const double rd = (double)r2.v[k];
           acc[0] += rd * rd;
@@ -651,16 +659,18 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
         }
       }
     }
-    // stage s1(j) for the next iteration's second sweep
 #pragma unroll
-    for (int k = 0; k < W; ++k) lds[j & 1][row][W * lane + k] = s1.v[k];
+    for (int k = 0; k < W; ++k) lds[j & 1][row][W * lane + k] = s1_j.v[k];
     __syncthreads();
-    s1_m2 = s1_m1;
-    s1_m1 = s1;
-    s_dn = s_c;
-    s_c = cur.s_up;
-    wz_c = cur.c.wzu;
-    cp = cur.c;
+  };
+  for (int j = jb; j <= je; j += 4) {
+    step(P[0], P[3], P[2], P[1], S1[0], S1[2], j);
+    if (j + 1 > je) break;
+    step(P[1], P[0], P[3], P[2], S1[1], S1[3], j + 1);
+    if (j + 2 > je) break;
+    step(P[2], P[1], P[0], P[3], S1[2], S1[0], j + 2);
+    if (j + 3 > je) break;
+    step(P[3], P[2], P[1], P[0], S1[3], S1[1], j + 3);
   }
   if (RES) block_store<NV>(acc, 0u, a.partial + (long long)NV * blockIdx.x);
 }
@@ -759,7 +769,8 @@ __global__ void __launch_bounds__(1024) k_sweep_v4(SweepArgs<float> a, int gx, i
 
 bool vec4_path(const Grid &g) { return (g.nx & 3) == 0; }
 
-bool two_path(const Grid &g) { return (g.nx % T2_W) == 0; }
+// even nx, and 32-bit element offsets for every FP32 array
+bool two_path(const Grid &g) { return (g.nx % T2_W) == 0 && g.n < (1ll << 30); }
 
 dim3 sweep2_grid(const Grid &g, const Tiles &t) {
   return dim3((unsigned)((g.nx + T2_OUT_X - 1) / T2_OUT_X),
