@@ -288,6 +288,7 @@ def main():
                      "kernel": "k_sweep2<correction> (FP32 correction sweeps, two per launch)",
                      "bytes_per_launch": 2 * BYTES_FP32_DC * ncell,
                      "bytes_per_cell_update": BYTES_FP32_DC, "avg_sweep_ms": avg32,
+                     "avg_launch_us": 2e3 * avg32,
                      "sweeps_timed": n32},
         "fp64_sweep": {"avg_ms": ms64 / n64 if n64 else None,
                        "achieved_GBs": BYTES_FP64 * ncell / (ms64 / n64 / 1e3) / 1e9 if n64 else None},
