@@ -80,6 +80,7 @@ struct socfv_ctx {
   double Q_in = 0, div_max = 0, u_max = 0;
   Tiles tiles{4, 8, 32, 1};
   bool tiles_fixed = false;
+  int ncu = 1;                   // compute units of the device (for the tile choice)
   // last forward solution
   bool have_state = false;
   int state_buf = 0;             // s64[state_buf] holds the last steady state
@@ -91,19 +92,35 @@ namespace {
 Faces<float> faces32(const socfv_ctx *c) { return {c->w32[0], c->w32[1], c->w32[2], c->w32[3]}; }
 Faces<double> faces64(const socfv_ctx *c) { return {c->w64[0], c->w64[1], c->w64[2], c->w64[3]}; }
 
-Tiles auto_tiles(const Grid &g, int ty) {
+// Two-sweep launches run one block per CU (its LDS and registers fill a CU), each block
+// marching one 124 x 14 output tile through a z chunk plus two extra planes.  The chunk
+// count is chosen to minimise (rounds of blocks over the CUs) x (planes per block), with
+// chunks of at least 8 planes unless nz is smaller.
+int pick_zc2(const Grid &g, int ncu) {
+  const long long t2 = (long long)((g.nx + 123) / 124) * ((g.ny + 13) / 14);
+  if (ncu < 1) ncu = 1;
+  long long best = -1;
+  int zbest = g.nz;
+  for (int c = 1; c <= g.nz; ++c) {
+    const int zc2 = (g.nz + c - 1) / c;
+    if (c > 1 && zc2 < 8) break;
+    const long long blocks = t2 * ((g.nz + zc2 - 1) / zc2);
+    const long long cost = (blocks + ncu - 1) / ncu * (zc2 + 2);
+    if (best < 0 || cost < best) {
+      best = cost;
+      zbest = zc2;
+    }
+  }
+  return zbest;
+}
+
+Tiles auto_tiles(const Grid &g, int ty, int ncu) {
   long long txy = (long long)((g.nx + 63) / 64) * ((g.ny + ty - 1) / ty);
   long long zc = (long long)g.nz * txy / 8192;
   if (zc < 1) zc = 1;
   if (zc > 32) zc = 32;
   if (zc > g.nz) zc = g.nz;
-  // two-sweep kernel: enough blocks to fill the chip, long z marches (2 extra planes each)
-  long long t2 = (long long)((g.nx + 123) / 124) * ((g.ny + 13) / 14);
-  long long zc2 = t2 > 0 ? (long long)g.nz * t2 / 2048 : g.nz;
-  if (zc2 < 8) zc2 = 8;
-  if (zc2 > 32) zc2 = 32;
-  if (zc2 > g.nz) zc2 = g.nz;
-  return Tiles{ty, (int)zc, (int)zc2, 1};
+  return Tiles{ty, (int)zc, pick_zc2(g, ncu), 1};
 }
 
 long long sweep_blocks(const Grid &g, const Tiles &t) {
@@ -512,9 +529,14 @@ int socfv_setup_geometry(socfv_ctx **out, int nx, int ny, int nz, const uint8_t 
   if (!solid) return fail(SOCFV_INVALID_ARG, "solid is NULL");
   const long long n = (long long)nx * ny * nz;
   if (n > (1ll << 40)) return fail(SOCFV_INVALID_ARG, "grid too large");
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return fail(SOCFV_HIP_ERROR, "device query failed");
   socfv_ctx *c = new socfv_ctx();
   c->g = Grid{nx, ny, nz, n};
-  c->tiles = auto_tiles(c->g, 16);
+  c->ncu = ncu;
+  c->tiles = auto_tiles(c->g, 16, ncu);
   auto bail = [&](int code) { socfv_destroy(c); return code; };
   if (hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess ||
@@ -825,7 +847,7 @@ int socfv_set_tiles(socfv_ctx *c, int tile_y, int z_chunk, int z_chunk2, int two
   if (tile_y != 0) {
     if (tile_y < 1 || tile_y > 16 || (tile_y & (tile_y - 1)))
       return fail(SOCFV_INVALID_ARG, "tile_y must be a power of two in [1, 16]");
-    Tiles t = auto_tiles(c->g, tile_y);
+    Tiles t = auto_tiles(c->g, tile_y, c->ncu);
     c->tiles.ty = tile_y;
     if (z_chunk == 0) c->tiles.zc = t.zc;
   }
@@ -899,7 +921,7 @@ int socfv_autotune(socfv_ctx *c, int sweeps, int best[3], void *hip_stream) {
   float best2 = 1e30f;
   int best_zc2 = c->tiles.zc2;
   if (two_path(c->g)) {
-    const int zc2s[] = {8, 16, 32, 64, 128};
+    const int zc2s[] = {pick_zc2(c->g, c->ncu), 8, 16, 32, 64, 128};
     for (int zc2 : zc2s) {
       if (zc2 > c->g.nz && zc2 != 8) continue;
       Tiles t = best_t;

@@ -469,6 +469,80 @@ struct CoefW {        // per-lane coefficients of one plane (W cells)
   unsigned fl;
 };
 
+// Resolved coefficients of W cells for the FP32 residual in the form
+//   R_P = src_P - s_P e_P + sum_f a_f (s_nb(f) - s_P),
+// a_f = max(inflow velocity through f, 0) + G_f (zero on closed faces and on the outlet
+// face, whose advective flux s_P w is part of e), e_P = div_P + lam_P, and src_P = lam_P s_eq,
+// or the frozen FP64 residual r0 for a correction (whose s_in and s_eq are 0).  Cells that
+// are not updated (fibre, held) get zero coefficients, so R = 0 there and a sweep keeps their
+// value, which the initial state sets (0 on fibre cells, s_eq or 0 on held cells).
+template <int W>
+struct ResW {
+  VecW<W> axm, axp, aym, ayp, azm, azp, e, src;
+};
+
+// max(w, 0) + G with one rounding, as the plain form: w + |w| is 2w or 0 exactly
+__device__ __forceinline__ float inflow_coef(float w, float G) {
+  return fmaf(0.5f, w + fabsf(w), G);
+}
+
+template <bool DC, int W>
+__device__ __forceinline__ void resolvew(const SweepArgs<float> &a, const CoefW<W> &c, int x,
+                                         int y, int z, bool up, long long i, ResW<W> &q) {
+  const int nx = a.g.nx, ny = a.g.ny;
+  // walls of this row / plane as closed-face bits (y, z)
+  const unsigned wall = (y > 0 ? 0u : (unsigned)FL_YM) | (y < ny - 1 ? 0u : (unsigned)FL_YP) |
+                        (z > 0 ? 0u : (unsigned)FL_ZM) | (up ? 0u : (unsigned)FL_ZP);
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const unsigned f = (c.fl >> (8 * k)) & 0xffu;
+    const int xk = x + k;
+    const bool outlet = xk == nx - 1;
+    const unsigned closed = f | wall;
+    const int nf = __popc(f & FL_FIBRE);
+    const bool upd = (f & FL_PORE) && !(a.pinned && nf > 0);
+    const float kap = a.kappa ? a.kappa[i + k] : 1.f;
+    const float lam = a.Da * kap * (float)nf;
+    const float wxm = c.wx.v[k], wxp = k == W - 1 ? c.wxr : c.wx.v[k + 1];
+    const float div = (wxp - wxm) + (c.wyp.v[k] - c.wym.v[k]) + (c.wzu.v[k] - c.wzl.v[k]);
+    // inlet face: Dirichlet value on the face, G = 2 (closed bit 0 is never set there)
+    const float axm = inflow_coef(wxm, gbit(closed, 0) + (xk == 0 ? 1.f : 0.f));
+    const float axp = outlet ? 0.f : inflow_coef(-wxp, gbit(closed, 1));
+    q.axm.v[k] = upd ? axm : 0.f;
+    q.axp.v[k] = upd ? axp : 0.f;
+    q.aym.v[k] = upd ? inflow_coef(c.wym.v[k], gbit(closed, 2)) : 0.f;
+    q.ayp.v[k] = upd ? inflow_coef(-c.wyp.v[k], gbit(closed, 3)) : 0.f;
+    q.azm.v[k] = upd ? inflow_coef(c.wzl.v[k], gbit(closed, 4)) : 0.f;
+    q.azp.v[k] = upd ? inflow_coef(-c.wzu.v[k], gbit(closed, 5)) : 0.f;
+    q.e.v[k] = upd ? div + lam : 0.f;
+    q.src.v[k] = upd ? (DC ? c.r0.v[k] : lam * a.s_eq) : 0.f;
+  }
+}
+
+// One explicit FP32 update of W cells from resolved coefficients: out = s + dt R(s),
+// rout = R.  left / right are the x neighbours beyond the lane's first / last cell.
+template <int W>
+__device__ __forceinline__ void applyw(const ResW<W> &q, float dt, const VecW<W> &sc,
+                                       float left, float right, const VecW<W> &sdn,
+                                       const VecW<W> &sup, const VecW<W> &sym,
+                                       const VecW<W> &syp, VecW<W> &out, VecW<W> &rout) {
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const float c0 = sc.v[k];
+    const float xm = k == 0 ? left : sc.v[k - 1];
+    const float xp = k == W - 1 ? right : sc.v[k + 1];
+    float r = fmaf(-c0, q.e.v[k], q.src.v[k]);
+    r = fmaf(q.axm.v[k], xm - c0, r);
+    r = fmaf(q.axp.v[k], xp - c0, r);
+    r = fmaf(q.aym.v[k], sym.v[k] - c0, r);
+    r = fmaf(q.ayp.v[k], syp.v[k] - c0, r);
+    r = fmaf(q.azm.v[k], sdn.v[k] - c0, r);
+    r = fmaf(q.azp.v[k], sup.v[k] - c0, r);
+    out.v[k] = fmaf(dt, r, c0);
+    rout.v[k] = r;
+  }
+}
+
 // One explicit FP32 sweep of W cells: out = s + dt (R(s) [+ r0]), rout = the residual used.
 template <bool DC, int W>
 __device__ __forceinline__ void sweepw(const SweepArgs<float> &a, const CoefW<W> &c,
@@ -477,36 +551,9 @@ __device__ __forceinline__ void sweepw(const SweepArgs<float> &a, const CoefW<W>
                                        const VecW<W> &sym, const VecW<W> &syp, int x, int y,
                                        int z, bool up, long long i, VecW<W> &out,
                                        VecW<W> &rout) {
-  const int nx = a.g.nx, ny = a.g.ny;
-  const bool yl = y > 0, yr = y < ny - 1;
-  // walls of this row / plane as closed-face bits (y, z); the outlet per cell below
-  const unsigned wall = (yl ? 0u : (unsigned)FL_YM) | (yr ? 0u : (unsigned)FL_YP) |
-                        (z > 0 ? 0u : (unsigned)FL_ZM) | (up ? 0u : (unsigned)FL_ZP);
-#pragma unroll
-  for (int k = 0; k < W; ++k) {
-    const unsigned f = (c.fl >> (8 * k)) & 0xffu;
-    const int xk = x + k;
-    const bool outlet = xk == nx - 1;
-    // inlet face: Dirichlet value on the face, G = 2 (closed bit 0 is never set there)
-    const unsigned closed = f | wall | (outlet ? (unsigned)FL_XP : 0u);
-    const float c0 = sc.v[k];
-    const float xm = k == 0 ? left : sc.v[k - 1];
-    const float xp = outlet ? c0 : (k == W - 1 ? right : sc.v[k + 1]);
-    const int nf = __popc(f & FL_FIBRE);
-    const bool held = a.pinned && nf > 0;
-    const float kap = a.kappa ? a.kappa[i + k] : 1.f;
-    float r = residual_fast(c0, xm, xp, sym.v[k], syp.v[k], sdn.v[k], sup.v[k], c.wx.v[k],
-                            k == W - 1 ? c.wxr : c.wx.v[k + 1], c.wym.v[k], c.wyp.v[k],
-                            c.wzl.v[k], c.wzu.v[k], closed, xk == 0 ? 1.f : 0.f,
-                            a.Da * kap * (float)nf, a.s_eq);
-    if (DC) r += c.r0.v[k];
-    const bool pore = f & FL_PORE;
-    if (held || !pore) r = 0.f;
-    float o = held ? (DC ? 0.f : a.s_eq) : c0 + a.dt * r;
-    if (!pore) o = 0.f;
-    out.v[k] = o;
-    rout.v[k] = r;
-  }
+  ResW<W> q;
+  resolvew<DC, W>(a, c, x, y, z, up, i, q);
+  applyw<W>(q, a.dt, sc, left, right, sdn, sup, sym, syp, out, rout);
 }
 
 // Everything a lane (two cells) reads from plane j: the state one plane up, the state of
@@ -517,10 +564,34 @@ struct Plane2 {
   float left, right;
 };
 
+// A lane's resolved coefficients (two cells) parked in LDS between its two sweeps of a
+// plane: four float4 per lane, lane-private (no barrier needed), two plane slots.
+__device__ __forceinline__ void park_coef(float4 (*slot)[64 * T2_ROWS], int t, const ResW<2> &q) {
+  slot[0][t] = make_float4(q.axm.v[0], q.axm.v[1], q.axp.v[0], q.axp.v[1]);
+  slot[1][t] = make_float4(q.aym.v[0], q.aym.v[1], q.ayp.v[0], q.ayp.v[1]);
+  slot[2][t] = make_float4(q.azm.v[0], q.azm.v[1], q.azp.v[0], q.azp.v[1]);
+  slot[3][t] = make_float4(q.e.v[0], q.e.v[1], q.src.v[0], q.src.v[1]);
+}
+
+__device__ __forceinline__ ResW<2> fetch_coef(float4 (*slot)[64 * T2_ROWS], int t) {
+  ResW<2> q;
+  float4 v = slot[0][t];
+  q.axm.v[0] = v.x; q.axm.v[1] = v.y; q.axp.v[0] = v.z; q.axp.v[1] = v.w;
+  v = slot[1][t];
+  q.aym.v[0] = v.x; q.aym.v[1] = v.y; q.ayp.v[0] = v.z; q.ayp.v[1] = v.w;
+  v = slot[2][t];
+  q.azm.v[0] = v.x; q.azm.v[1] = v.y; q.azp.v[0] = v.z; q.azp.v[1] = v.w;
+  v = slot[3][t];
+  q.e.v[0] = v.x; q.e.v[1] = v.y; q.src.v[0] = v.z; q.src.v[1] = v.w;
+  return q;
+}
+
 // Loads at clamped 32-bit offsets (every address valid; out-of-range planes, rows and
 // lanes read a copy of a valid cell and their results meet only zero-coefficient faces),
 // then selects for the wall velocities that must be zero.
-template <bool DC>
+// With UPZ the plane's upper z-face velocity is loaded too; without, the caller takes it
+// from the next plane's lower face.
+template <bool DC, bool UPZ>
 __device__ __forceinline__ void load_plane2(const SweepArgs<float> &a, Plane2 &d, unsigned ib,
                                             unsigned pl, int j, int xc, int yc, int lane,
                                             bool last, bool yl, bool yr) {
@@ -538,12 +609,13 @@ __device__ __forceinline__ void load_plane2(const SweepArgs<float> &a, Plane2 &d
   d.c.wym = ldw<2>(a.w.wy + o);
   const VecW<2> wyp = ldw<2>(a.w.wy + oyp);
   d.c.wzl = ldw<2>(a.w.wz + o);
-  const VecW<2> wzu = ldw<2>(a.w.wz + oup);
+  if (UPZ) {
+    const VecW<2> wzu = ldw<2>(a.w.wz + oup);
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    d.c.wyp.v[k] = yr ? wyp.v[k] : 0.f;
-    d.c.wzu.v[k] = up ? wzu.v[k] : 0.f;
+    for (int k = 0; k < 2; ++k) d.c.wzu.v[k] = up ? wzu.v[k] : 0.f;
   }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) d.c.wyp.v[k] = yr ? wyp.v[k] : 0.f;
   d.c.fl = ldflags<2>(a.flags + o);
   if (DC) d.c.r0 = ldw<2>(a.r0 + o);
   else d.c.r0 = zerow<2>();
@@ -562,12 +634,13 @@ template <bool DC, bool RES>
 __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int gy, int gz) {
   constexpr int W = T2_W;
   __shared__ float lds[2][T2_ROWS][64 * W];
+  __shared__ float4 qlds[2][4][64 * T2_ROWS];
   const Grid g = a.g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int nb = gx * gy * gz;
   const int L = xcd_tile(blockIdx.x, nb);
   const int bx = L % gx, by = (L / gx) % gy, bz = L / (gx * gy);
-  const int lane = threadIdx.x, row = threadIdx.y;
+  const int lane = threadIdx.x, row = threadIdx.y, tid = lane + 64 * row;
   const int x = bx * T2_OUT_X - W + W * lane;
   const int y = by * T2_OUT_Y - 1 + row;
   const int z0 = bz * a.zc;
@@ -584,26 +657,33 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
   double acc[NV] = {0, 0, 0, 0};
   // March j over [jb, je]: first sweep at plane j, second sweep at plane j-1 from the LDS
   // copy of s1(j-1) staged in the previous step, stage s1(j).  Plane data sit in a ring of
-  // four (j+1 is fetched while j is swept; j-1 feeds the second sweep; j-2 holds s(j-1))
-  // and first-sweep results in a ring of four; the loop is unrolled by four so every ring
-  // index is a compile-time constant.
+  // four: j is swept, j-1 keeps s(j) (its s_up), and the loads of the next PD planes are in
+  // flight (two ahead; one in the variant that also accumulates the residual, whose extra
+  // registers would not fit two).  First-sweep results sit in a ring of four; the loop is
+  // unrolled by four so every ring index is a compile-time constant.
+  constexpr int PD = RES ? 1 : 2;
   const int jb = max(z0 - 1, 0);
   const int je = min(z1, nz);            // inclusive; j == nz only finishes plane nz-1
   Plane2 P[4];
-  VecW<W> S1[4];
-  S1[0] = S1[1] = S1[2] = S1[3] = zw;
+  VecW<W> sdn;                           // s(j-1)
+  // first-sweep planes below the box are closed walls: their LDS copy must be finite
+#pragma unroll
+  for (int k = 0; k < W; ++k) lds[0][row][W * lane + k] = lds[1][row][W * lane + k] = 0.f;
   {
     const unsigned o = ib + pl * (unsigned)jb;
-    P[2].s_up = jb > 0 ? ldw<W>(a.s + o - pl) : zw;     // s(jb-1)
-    P[3].s_up = ldw<W>(a.s + o);                        // s(jb)
-    P[3].c.wx = P[3].c.wym = P[3].c.wyp = P[3].c.wzl = P[3].c.wzu = P[3].c.r0 = zw;
+    sdn = jb > 0 ? ldw<W>(a.s + o - pl) : zw;
+    P[3].s_up = ldw<W>(a.s + o);         // s(jb)
     P[3].c.fl = 0u;
-    P[3].c.wxr = 0.f;
-    load_plane2<DC>(a, P[0], ib, pl, jb, xc, yc, lane, last, yl, yr);
+    load_plane2<DC, PD == 1>(a, P[0], ib, pl, jb, xc, yc, lane, last, yl, yr);
+    if (PD == 2) load_plane2<DC, false>(a, P[1], ib, pl, jb + 1, xc, yc, lane, last, yl, yr);
   }
-  auto step = [&](Plane2 &cur, const Plane2 &prev, const Plane2 &pprev, Plane2 &nxt,
-                  VecW<W> &s1_j, const VecW<W> &s1_jm2, int j) {
-    load_plane2<DC>(a, nxt, ib, pl, j + 1, xc, yc, lane, last, yl, yr);
+  auto step = [&](Plane2 &cur, const Plane2 &prev, const Plane2 &nxt, Plane2 &ld, int j) {
+    load_plane2<DC, PD == 1>(a, ld, ib, pl, j + PD, xc, yc, lane, last, yl, yr);
+    if (PD == 2) {
+      // upper z face of plane j = lower z face of plane j+1 (closed above the top plane)
+#pragma unroll
+      for (int k = 0; k < W; ++k) cur.c.wzu.v[k] = j + 1 < nz ? nxt.c.wzl.v[k] : 0.f;
+    }
     const VecW<W> &s_c = prev.s_up;      // s(j)
     float left = __shfl_up(s_c.v[W - 1], 1, 64);
     float right = __shfl_down(s_c.v[0], 1, 64);
@@ -614,33 +694,36 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
       wxr = cur.c.wxr;
     }
     if (x == 0) left = a.s_in;
-    // the resolved face velocity stays with the plane: the second sweep reads it next step
     cur.c.wxr = wxr;
-    VecW<W> r1;
+    VecW<W> r1, s1_j;
     if (j < nz) {
-      sweepw<DC, W>(a, cur.c, s_c, left, right, pprev.s_up, cur.s_up, cur.sym, cur.syp, xc, yc,
-                    j, j + 1 < nz, ib + pl * (unsigned)j, s1_j, r1);
+      ResW<W> q;
+      resolvew<DC, W>(a, cur.c, xc, yc, j, j + 1 < nz, ib + pl * (unsigned)j, q);
+      applyw<W>(q, a.dt, s_c, left, right, sdn, cur.s_up, cur.sym, cur.syp, s1_j, r1);
+      park_coef(qlds[j & 1], tid, q);
     } else {
       s1_j = zw;
     }
+    sdn = s_c;
     // second sweep at plane p = j - 1 on the interior
     const int p = j - 1;
     if (p >= z0 && p < z1 && outc) {
       const int bp = p & 1;
-      VecW<W> c1, ym1, yp1;
+      // s1(p) and its y neighbours, and the lane's own s1(p-1) below: the other slot still
+      // holds it, as s1(j) is staged only at the end of this step
+      VecW<W> c1, ym1, yp1, dn1;
 #pragma unroll
       for (int k = 0; k < W; ++k) {
         c1.v[k] = lds[bp][row][W * lane + k];
         ym1.v[k] = lds[bp][row - 1][W * lane + k];
         yp1.v[k] = lds[bp][row + 1][W * lane + k];
+        dn1.v[k] = lds[bp ^ 1][row][W * lane + k];
       }
       const float lft = x == 0 ? a.s_in : lds[bp][row][W * lane - 1];
       const float rgt = lds[bp][row][W * lane + W];
-      const bool upp = p + 1 < nz;
       const unsigned ip = ib + pl * (unsigned)p;
       VecW<W> s2, r2;
-      sweepw<DC, W>(a, prev.c, c1, lft, rgt, s1_jm2, upp ? s1_j : zw, ym1, yp1, x, y, p, upp,
-                    ip, s2, r2);
+      applyw<W>(fetch_coef(qlds[bp], tid), a.dt, c1, lft, rgt, dn1, s1_j, ym1, yp1, s2, r2);
       stw<W>(a.s_new + ip, s2);
       if (RES) {
 #pragma unroll
@@ -664,13 +747,13 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
     __syncthreads();
   };
   for (int j = jb; j <= je; j += 4) {
-    step(P[0], P[3], P[2], P[1], S1[0], S1[2], j);
+    step(P[0], P[3], P[1], P[(PD + 0) & 3], j);
     if (j + 1 > je) break;
-    step(P[1], P[0], P[3], P[2], S1[1], S1[3], j + 1);
+    step(P[1], P[0], P[2], P[(PD + 1) & 3], j + 1);
     if (j + 2 > je) break;
-    step(P[2], P[1], P[0], P[3], S1[2], S1[0], j + 2);
+    step(P[2], P[1], P[3], P[(PD + 2) & 3], j + 2);
     if (j + 3 > je) break;
-    step(P[3], P[2], P[1], P[0], S1[3], S1[1], j + 3);
+    step(P[3], P[2], P[0], P[(PD + 3) & 3], j + 3);
   }
   if (RES) block_store<NV>(acc, 0u, a.partial + (long long)NV * blockIdx.x);
 }

@@ -291,3 +291,32 @@ def test_two_sweep_launches_match_single_sweeps(sv, shape):
         b, nb = out[(1, prec)]
         assert na == nb
         assert np.abs(a - b).max() <= 1e-6, (prec, np.abs(a - b).max())
+
+
+@pytest.mark.parametrize("variant", ["pinned", "activity"])
+def test_two_sweep_launches_match_single_sweeps_modes(sv, orc, variant):
+    """The same with held cells (pinned mode) and with a per-cell activity and s_eq > 0 (the
+    plain form's source term): fibre cells stay 0 and held cells s_eq exactly."""
+    solid, u = fibre_case(128, 40, 33, 3.0, 0.85, 32, 1.0)
+    kappa = I.lognormal_activity(solid, 0.3, seed=7) if variant == "activity" else None
+    pb = make(sv, solid, u, kappa=kappa)
+    if variant == "pinned":
+        kw = dict(mode=1, s_in=0.0, s_eq=1.0, Da=0.0)
+    else:
+        kw = dict(s_in=0.9, s_eq=0.3, Da=0.45)
+    out = {}
+    for two in (0, 1):
+        sv.set_tiles(pb.ctx, 0, 0, 0, two)
+        for prec in ("fp32_plain", "fp32"):
+            p = sv.params(precision=prec, tol=0.0, max_iter=400, check_every=200, **kw)
+            s, st = sv.solve_soc_steady(pb.ctx, p)
+            out[(two, prec)] = (s.cpu().numpy(), st.iterations)
+    nf = orc.fibre_faces(solid)
+    held = (nf > 0) & (solid == 0) if variant == "pinned" else np.zeros(solid.shape, bool)
+    for prec in ("fp32_plain", "fp32"):
+        a, na = out[(0, prec)]
+        b, nb = out[(1, prec)]
+        assert na == nb
+        assert np.abs(a - b).max() <= 1e-6, (prec, np.abs(a - b).max())
+        assert np.all(b[solid == 1] == 0.0)
+        assert np.all(b[held] == kw["s_eq"])
