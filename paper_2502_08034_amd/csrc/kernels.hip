@@ -17,6 +17,7 @@
 #include "internal.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace socfv {
 
@@ -406,7 +407,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // FP32 sweep with four consecutive x cells per lane (16-byte loads and stores); rows of
 // 256 cells per wave.  Used when nx is a multiple of 4.  The x neighbours of a lane's
 // group come from the adjacent lanes by shuffles; the wave's edge lanes load them.
-template <bool DC, bool RES>
+template <bool DC, bool RES, bool ACT>
 __global__ void __launch_bounds__(1024) k_sweep_v4(SweepArgs<float> a, int gx, int gy, int gz);
 
 // Two sweeps per launch (time skewing along the z march).  A block of 64 x 16 lanes holds
@@ -465,6 +466,7 @@ __device__ __forceinline__ VecW<W> zerow() {
 template <int W>
 struct CoefW {        // per-lane coefficients of one plane (W cells)
   VecW<W> wx, wym, wyp, wzl, wzu, r0;
+  VecW<W> kap;        // per-cell activity (kernels instantiated for an activity field)
   float wxr;          // x face velocity after the lane's last cell
   unsigned fl;
 };
@@ -481,14 +483,18 @@ struct ResW {
   VecW<W> axm, axp, aym, ayp, azm, azp, e, src;
 };
 
-// max(w, 0) + G with one rounding, as the plain form: w + |w| is 2w or 0 exactly
-__device__ __forceinline__ float inflow_coef(float w, float G) {
-  return fmaf(0.5f, w + fabsf(w), G);
+// max(w, 0) + G with one rounding (h = 1/2): w + |w| is 2w or 0 exactly.  With h = 0 and
+// G = 0 the coefficient is 0, which is how cells that are not updated get theirs without
+// a branch.
+__device__ __forceinline__ float inflow_coef(float h, float w, float G) {
+  return fmaf(h, w + fabsf(w), G);
 }
 
-template <bool DC, int W>
+// ACT: the activity field is set and its values came with the plane's loads (a load here
+// would make the step wait for every load in flight).
+template <bool DC, bool ACT, int W>
 __device__ __forceinline__ void resolvew(const SweepArgs<float> &a, const CoefW<W> &c, int x,
-                                         int y, int z, bool up, long long i, ResW<W> &q) {
+                                         int y, int z, bool up, ResW<W> &q) {
   const int nx = a.g.nx, ny = a.g.ny;
   // walls of this row / plane as closed-face bits (y, z)
   const unsigned wall = (y > 0 ? 0u : (unsigned)FL_YM) | (y < ny - 1 ? 0u : (unsigned)FL_YP) |
@@ -498,24 +504,26 @@ __device__ __forceinline__ void resolvew(const SweepArgs<float> &a, const CoefW<
     const unsigned f = (c.fl >> (8 * k)) & 0xffu;
     const int xk = x + k;
     const bool outlet = xk == nx - 1;
-    const unsigned closed = f | wall;
     const int nf = __popc(f & FL_FIBRE);
     const bool upd = (f & FL_PORE) && !(a.pinned && nf > 0);
-    const float kap = a.kappa ? a.kappa[i + k] : 1.f;
-    const float lam = a.Da * kap * (float)nf;
+    // not updated: every face closed and no advective part
+    const unsigned closed = upd ? (f | wall) : (unsigned)FL_FIBRE;
+    const float h = upd ? 0.5f : 0.f;
+    const float lam = a.Da * (ACT ? c.kap.v[k] : 1.f) * (float)nf;
     const float wxm = c.wx.v[k], wxp = k == W - 1 ? c.wxr : c.wx.v[k + 1];
     const float div = (wxp - wxm) + (c.wyp.v[k] - c.wym.v[k]) + (c.wzu.v[k] - c.wzl.v[k]);
-    // inlet face: Dirichlet value on the face, G = 2 (closed bit 0 is never set there)
-    const float axm = inflow_coef(wxm, gbit(closed, 0) + (xk == 0 ? 1.f : 0.f));
-    const float axp = outlet ? 0.f : inflow_coef(-wxp, gbit(closed, 1));
-    q.axm.v[k] = upd ? axm : 0.f;
-    q.axp.v[k] = upd ? axp : 0.f;
-    q.aym.v[k] = upd ? inflow_coef(c.wym.v[k], gbit(closed, 2)) : 0.f;
-    q.ayp.v[k] = upd ? inflow_coef(-c.wyp.v[k], gbit(closed, 3)) : 0.f;
-    q.azm.v[k] = upd ? inflow_coef(c.wzl.v[k], gbit(closed, 4)) : 0.f;
-    q.azp.v[k] = upd ? inflow_coef(-c.wzu.v[k], gbit(closed, 5)) : 0.f;
-    q.e.v[k] = upd ? div + lam : 0.f;
-    q.src.v[k] = upd ? (DC ? c.r0.v[k] : lam * a.s_eq) : 0.f;
+    // inlet face: Dirichlet value on the face, G = 2 (closed bit 0 is never set there); the
+    // outlet face's flux s_P w is all in e
+    q.axm.v[k] = inflow_coef(h, wxm, gbit(closed, 0) + (upd && xk == 0 ? 1.f : 0.f));
+    q.axp.v[k] = inflow_coef(h, outlet ? 0.f : -wxp, outlet ? 0.f : gbit(closed, 1));
+    q.aym.v[k] = inflow_coef(h, c.wym.v[k], gbit(closed, 2));
+    q.ayp.v[k] = inflow_coef(h, -c.wyp.v[k], gbit(closed, 3));
+    q.azm.v[k] = inflow_coef(h, c.wzl.v[k], gbit(closed, 4));
+    q.azp.v[k] = inflow_coef(h, -c.wzu.v[k], gbit(closed, 5));
+    const float e = div + lam;
+    const float src = DC ? c.r0.v[k] : lam * a.s_eq;
+    q.e.v[k] = upd ? e : 0.f;
+    q.src.v[k] = upd ? src : 0.f;
   }
 }
 
@@ -544,15 +552,14 @@ __device__ __forceinline__ void applyw(const ResW<W> &q, float dt, const VecW<W>
 }
 
 // One explicit FP32 sweep of W cells: out = s + dt (R(s) [+ r0]), rout = the residual used.
-template <bool DC, int W>
+template <bool DC, bool ACT, int W>
 __device__ __forceinline__ void sweepw(const SweepArgs<float> &a, const CoefW<W> &c,
                                        const VecW<W> &sc, float left, float right,
                                        const VecW<W> &sdn, const VecW<W> &sup,
                                        const VecW<W> &sym, const VecW<W> &syp, int x, int y,
-                                       int z, bool up, long long i, VecW<W> &out,
-                                       VecW<W> &rout) {
+                                       int z, bool up, VecW<W> &out, VecW<W> &rout) {
   ResW<W> q;
-  resolvew<DC, W>(a, c, x, y, z, up, i, q);
+  resolvew<DC, ACT, W>(a, c, x, y, z, up, q);
   applyw<W>(q, a.dt, sc, left, right, sdn, sup, sym, syp, out, rout);
 }
 
@@ -586,51 +593,70 @@ __device__ __forceinline__ ResW<2> fetch_coef(float4 (*slot)[64 * T2_ROWS], int 
   return q;
 }
 
+// Loads and stores at a 32-bit byte offset from a kernel-argument base: the compiler then
+// addresses with the scalar base plus one 32-bit VGPR offset per lane, with no 64-bit
+// address arithmetic per access.  Every FP32 array of the two-sweep path is below 4 GiB.
+__device__ __forceinline__ VecW<2> ldo2(const float *base, unsigned off) {
+  return ldw<2>(reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + off));
+}
+
+__device__ __forceinline__ float ldo1(const float *base, unsigned off) {
+  return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + off);
+}
+
+__device__ __forceinline__ void sto2(float *base, unsigned off, const VecW<2> &v) {
+  stw<2>(reinterpret_cast<float *>(reinterpret_cast<char *>(base) + off), v);
+}
+
 // Loads at clamped 32-bit offsets (every address valid; out-of-range planes, rows and
 // lanes read a copy of a valid cell and their results meet only zero-coefficient faces),
-// then selects for the wall velocities that must be zero.
-// With UPZ the plane's upper z-face velocity is loaded too; without, the caller takes it
-// from the next plane's lower face.
-template <bool DC, bool UPZ>
-__device__ __forceinline__ void load_plane2(const SweepArgs<float> &a, Plane2 &d, unsigned ib,
-                                            unsigned pl, int j, int xc, int yc, int lane,
-                                            bool last, bool yl, bool yr) {
+// then selects for the wall velocities that must be zero.  With UPZ the plane's upper
+// z-face velocity is loaded too; without, the caller takes it from the next plane's lower
+// face.
+template <bool DC, bool UPZ, bool ACT>
+__device__ __forceinline__ void load_plane2(const SweepArgs<float> &a, Plane2 &d,
+                                            unsigned ib, unsigned pl, int j, int xc, int yc,
+                                            int lane, bool last, bool yl, bool yr) {
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
   const int jj = min(j, nz - 1);
   const bool up = jj + 1 < nz;
   const unsigned o = ib + pl * (unsigned)jj;
-  const unsigned oup = o + (up ? pl : 0u);
-  const unsigned oyp = o + (yr ? (unsigned)nx : 0u);
-  const unsigned oym = o - (yl ? (unsigned)nx : 0u);
-  d.s_up = ldw<2>(a.s + oup);
-  d.sym = ldw<2>(a.s + oym);
-  d.syp = ldw<2>(a.s + oyp);
-  d.c.wx = ldw<2>(a.w.wx + o);
-  d.c.wym = ldw<2>(a.w.wy + o);
-  const VecW<2> wyp = ldw<2>(a.w.wy + oyp);
-  d.c.wzl = ldw<2>(a.w.wz + o);
+  const unsigned o4 = 4u * o;
+  const unsigned oup = o4 + (up ? 4u * pl : 0u);
+  const unsigned oyp = o4 + (yr ? 4u * (unsigned)nx : 0u);
+  const unsigned oym = o4 - (yl ? 4u * (unsigned)nx : 0u);
+  // the lower z face first: the step before this plane's reads it as its upper face, and
+  // load counters complete in issue order
+  d.c.wzl = ldo2(a.w.wz, o4);
+  d.s_up = ldo2(a.s, oup);
+  d.sym = ldo2(a.s, oym);
+  d.syp = ldo2(a.s, oyp);
+  d.c.wx = ldo2(a.w.wx, o4);
+  d.c.wym = ldo2(a.w.wy, o4);
+  const VecW<2> wyp = ldo2(a.w.wy, oyp);
   if (UPZ) {
-    const VecW<2> wzu = ldw<2>(a.w.wz + oup);
+    const VecW<2> wzu = ldo2(a.w.wz, oup);
 #pragma unroll
     for (int k = 0; k < 2; ++k) d.c.wzu.v[k] = up ? wzu.v[k] : 0.f;
   }
 #pragma unroll
   for (int k = 0; k < 2; ++k) d.c.wyp.v[k] = yr ? wyp.v[k] : 0.f;
   d.c.fl = ldflags<2>(a.flags + o);
-  if (DC) d.c.r0 = ldw<2>(a.r0 + o);
+  if (DC) d.c.r0 = ldo2(a.r0, o4);
   else d.c.r0 = zerow<2>();
+  if (ACT) d.c.kap = ldo2(a.kappa, o4);
   d.left = a.s_in;
   d.right = 0.f;
   d.c.wxr = 0.f;
-  if (lane == 0 && xc > 0) d.left = a.s[o - 1];
-  if (last) d.c.wxr = a.w.wxo[yc + (unsigned)ny * (unsigned)jj];
+  if (lane == 0 && xc > 0) d.left = ldo1(a.s, o4 - 4u);
+  if (last) d.c.wxr = ldo1(a.w.wxo, 4u * (yc + (unsigned)ny * (unsigned)jj));
   else if (lane == 63) {
-    d.right = a.s[o + 2];
-    d.c.wxr = a.w.wx[o + 2];
+    d.right = ldo1(a.s, o4 + 8u);
+    d.c.wxr = ldo1(a.w.wx, o4 + 8u);
   }
 }
 
-template <bool DC, bool RES>
+template <bool DC, bool RES, bool ACT>
 __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int gy, int gz) {
   constexpr int W = T2_W;
   __shared__ float lds[2][T2_ROWS][64 * W];
@@ -661,7 +687,7 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
   // flight (two ahead; one in the variant that also accumulates the residual, whose extra
   // registers would not fit two).  First-sweep results sit in a ring of four; the loop is
   // unrolled by four so every ring index is a compile-time constant.
-  constexpr int PD = RES ? 1 : 2;
+  constexpr int PD = RES || ACT ? 1 : 2;
   const int jb = max(z0 - 1, 0);
   const int je = min(z1, nz);            // inclusive; j == nz only finishes plane nz-1
   Plane2 P[4];
@@ -671,14 +697,14 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
   for (int k = 0; k < W; ++k) lds[0][row][W * lane + k] = lds[1][row][W * lane + k] = 0.f;
   {
     const unsigned o = ib + pl * (unsigned)jb;
-    sdn = jb > 0 ? ldw<W>(a.s + o - pl) : zw;
-    P[3].s_up = ldw<W>(a.s + o);         // s(jb)
+    sdn = jb > 0 ? ldo2(a.s, 4u * (o - pl)) : zw;
+    P[3].s_up = ldo2(a.s, 4u * o);       // s(jb)
     P[3].c.fl = 0u;
-    load_plane2<DC, PD == 1>(a, P[0], ib, pl, jb, xc, yc, lane, last, yl, yr);
-    if (PD == 2) load_plane2<DC, false>(a, P[1], ib, pl, jb + 1, xc, yc, lane, last, yl, yr);
+    load_plane2<DC, PD == 1, ACT>(a, P[0], ib, pl, jb, xc, yc, lane, last, yl, yr);
+    if (PD == 2) load_plane2<DC, false, ACT>(a, P[1], ib, pl, jb + 1, xc, yc, lane, last, yl, yr);
   }
   auto step = [&](Plane2 &cur, const Plane2 &prev, const Plane2 &nxt, Plane2 &ld, int j) {
-    load_plane2<DC, PD == 1>(a, ld, ib, pl, j + PD, xc, yc, lane, last, yl, yr);
+    load_plane2<DC, PD == 1, ACT>(a, ld, ib, pl, j + PD, xc, yc, lane, last, yl, yr);
     if (PD == 2) {
       // upper z face of plane j = lower z face of plane j+1 (closed above the top plane)
 #pragma unroll
@@ -698,7 +724,7 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
     VecW<W> r1, s1_j;
     if (j < nz) {
       ResW<W> q;
-      resolvew<DC, W>(a, cur.c, xc, yc, j, j + 1 < nz, ib + pl * (unsigned)j, q);
+      resolvew<DC, ACT, W>(a, cur.c, xc, yc, j, j + 1 < nz, q);
       applyw<W>(q, a.dt, s_c, left, right, sdn, cur.s_up, cur.sym, cur.syp, s1_j, r1);
       park_coef(qlds[j & 1], tid, q);
     } else {
@@ -724,7 +750,7 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
       const unsigned ip = ib + pl * (unsigned)p;
       VecW<W> s2, r2;
       applyw<W>(fetch_coef(qlds[bp], tid), a.dt, c1, lft, rgt, dn1, s1_j, ym1, yp1, s2, r2);
-      stw<W>(a.s_new + ip, s2);
+      sto2(a.s_new, 4u * ip, s2);
       if (RES) {
 #pragma unroll
         for (int k = 0; k < W; ++k) {
@@ -758,7 +784,7 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
   if (RES) block_store<NV>(acc, 0u, a.partial + (long long)NV * blockIdx.x);
 }
 
-template <bool DC, bool RES>
+template <bool DC, bool RES, bool ACT>
 __global__ void __launch_bounds__(1024) k_sweep_v4(SweepArgs<float> a, int gx, int gy, int gz) {
   constexpr int W = 4;
   const Grid g = a.g;
@@ -805,6 +831,7 @@ __global__ void __launch_bounds__(1024) k_sweep_v4(SweepArgs<float> a, int gx, i
       if (yl) sym = ldw<W>(a.s + i - nx);
       cc.fl = ldflags<W>(a.flags + i);
       if (DC) cc.r0 = ldw<W>(a.r0 + i);
+      if (ACT) cc.kap = ldw<W>(a.kappa + i);
     }
     // x neighbours: lane-1 holds x-1, lane+1 holds x+4 and the face velocity at x+4
     float left = __shfl_up(sc.v[W - 1], 1, 64);
@@ -824,7 +851,7 @@ __global__ void __launch_bounds__(1024) k_sweep_v4(SweepArgs<float> a, int gx, i
     cc.wxr = wxr;
     if (act) {
       VecW<W> out, r;
-      sweepw<DC, W>(a, cc, sc, left, right, sdn, sup, sym, syp, x, y, z, up, i, out, r);
+      sweepw<DC, ACT, W>(a, cc, sc, left, right, sdn, sup, sym, syp, x, y, z, up, out, r);
       stw<W>(a.s_new + i, out);
       if (RES) {
 #pragma unroll
@@ -861,20 +888,31 @@ dim3 sweep2_grid(const Grid &g, const Tiles &t) {
               (unsigned)((g.nz + t.zc2 - 1) / t.zc2));
 }
 
+// Calls f with three std::bool_constant arguments, so one launch line covers the eight
+// instantiations of a kernel template over (correction, residual, activity).
+template <typename F>
+void with_flags(bool a, bool b, bool c, F &&f) {
+  using T = std::true_type;
+  using N = std::false_type;
+  if (a) {
+    if (b) { if (c) f(T{}, T{}, T{}); else f(T{}, T{}, N{}); }
+    else { if (c) f(T{}, N{}, T{}); else f(T{}, N{}, N{}); }
+  } else {
+    if (b) { if (c) f(N{}, T{}, T{}); else f(N{}, T{}, N{}); }
+    else { if (c) f(N{}, N{}, T{}); else f(N{}, N{}, N{}); }
+  }
+}
+
 void launch_sweep2(const SweepArgs<float> &a, const Tiles &t, hipStream_t st) {
   dim3 gv = sweep2_grid(a.g, t);
   const unsigned nb = gv.x * gv.y * gv.z;
   SweepArgs<float> b = a;
   b.zc = t.zc2;
   dim3 block(64, T2_ROWS, 1);
-  const bool dc = a.r0 != nullptr, res = a.partial != nullptr;
-  if (dc) {
-    if (res) k_sweep2<true, true><<<nb, block, 0, st>>>(b, gv.x, gv.y, gv.z);
-    else k_sweep2<true, false><<<nb, block, 0, st>>>(b, gv.x, gv.y, gv.z);
-  } else {
-    if (res) k_sweep2<false, true><<<nb, block, 0, st>>>(b, gv.x, gv.y, gv.z);
-    else k_sweep2<false, false><<<nb, block, 0, st>>>(b, gv.x, gv.y, gv.z);
-  }
+  with_flags(a.r0 != nullptr, a.partial != nullptr, a.kappa != nullptr,
+             [&](auto dc, auto res, auto act) {
+               k_sweep2<dc.value, res.value, act.value><<<nb, block, 0, st>>>(b, gv.x, gv.y, gv.z);
+             });
 }
 
 dim3 sweep_grid_v4(const Grid &g, const Tiles &t) {
@@ -889,14 +927,11 @@ void launch_sweep(const SweepArgs<T> &a, const Tiles &t, hipStream_t st) {
     dim3 gv = sweep_grid_v4(a.g, t);
     const unsigned nb = gv.x * gv.y * gv.z;
     dim3 block(64, t.ty, 1);
-    const bool dc = a.r0 != nullptr, res = a.partial != nullptr;
-    if (dc) {
-      if (res) k_sweep_v4<true, true><<<nb, block, 0, st>>>(af, gv.x, gv.y, gv.z);
-      else k_sweep_v4<true, false><<<nb, block, 0, st>>>(af, gv.x, gv.y, gv.z);
-    } else {
-      if (res) k_sweep_v4<false, true><<<nb, block, 0, st>>>(af, gv.x, gv.y, gv.z);
-      else k_sweep_v4<false, false><<<nb, block, 0, st>>>(af, gv.x, gv.y, gv.z);
-    }
+    with_flags(a.r0 != nullptr, a.partial != nullptr, a.kappa != nullptr,
+               [&](auto dc, auto res, auto act) {
+                 k_sweep_v4<dc.value, res.value, act.value><<<nb, block, 0, st>>>(af, gv.x, gv.y,
+                                                                                 gv.z);
+               });
     return;
   }
   dim3 grid = sweep_grid(a.g, t), block(64, t.ty, 1);
