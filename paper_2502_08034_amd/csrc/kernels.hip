@@ -571,6 +571,19 @@ struct Plane2 {
   float left, right;
 };
 
+// One-lane shifts across the wave by DPP wave shifts (one VALU move, no LDS round trip):
+// lane i receives lane i-1's value (from below) or lane i+1's (from above); the wave's
+// first / last lane receives 0.  Every lane whose value is read must be active.
+__device__ __forceinline__ float lane_from_below(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               0x138, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ float lane_from_above(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               0x130, 0xf, 0xf, false));
+}
+
 // A lane's resolved coefficients (two cells) parked in LDS between its two sweeps of a
 // plane: four float4 per lane, lane-private (no barrier needed), two plane slots.
 __device__ __forceinline__ void park_coef(float4 (*slot)[64 * T2_ROWS], int t, const ResW<2> &q) {
@@ -711,9 +724,9 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
       for (int k = 0; k < W; ++k) cur.c.wzu.v[k] = j + 1 < nz ? nxt.c.wzl.v[k] : 0.f;
     }
     const VecW<W> &s_c = prev.s_up;      // s(j)
-    float left = __shfl_up(s_c.v[W - 1], 1, 64);
-    float right = __shfl_down(s_c.v[0], 1, 64);
-    float wxr = __shfl_down(cur.c.wx.v[0], 1, 64);
+    float left = lane_from_below(s_c.v[W - 1]);
+    float right = lane_from_above(s_c.v[0]);
+    float wxr = lane_from_above(cur.c.wx.v[0]);
     if (lane == 0) left = cur.left;
     if (lane == 63 || last) {
       right = cur.right;
@@ -731,22 +744,28 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
       s1_j = zw;
     }
     sdn = s_c;
-    // second sweep at plane p = j - 1 on the interior
+    // second sweep at plane p = j - 1 on the interior.  The lane's own s1(p) is read and
+    // its x neighbours shifted in from the adjacent lanes with every lane active (the halo
+    // lanes take no part in the update below but supply these values).
     const int p = j - 1;
+    const int bp = p & 1;
+    VecW<W> c1;
+#pragma unroll
+    for (int k = 0; k < W; ++k) c1.v[k] = lds[bp][row][W * lane + k];
+    const float c1_left = lane_from_below(c1.v[W - 1]);
+    const float c1_right = lane_from_above(c1.v[0]);
     if (p >= z0 && p < z1 && outc) {
-      const int bp = p & 1;
-      // s1(p) and its y neighbours, and the lane's own s1(p-1) below: the other slot still
+      // y neighbours of s1(p), and the lane's own s1(p-1) below: the other slot still
       // holds it, as s1(j) is staged only at the end of this step
-      VecW<W> c1, ym1, yp1, dn1;
+      VecW<W> ym1, yp1, dn1;
 #pragma unroll
       for (int k = 0; k < W; ++k) {
-        c1.v[k] = lds[bp][row][W * lane + k];
         ym1.v[k] = lds[bp][row - 1][W * lane + k];
         yp1.v[k] = lds[bp][row + 1][W * lane + k];
         dn1.v[k] = lds[bp ^ 1][row][W * lane + k];
       }
-      const float lft = x == 0 ? a.s_in : lds[bp][row][W * lane - 1];
-      const float rgt = lds[bp][row][W * lane + W];
+      const float lft = x == 0 ? a.s_in : c1_left;
+      const float rgt = c1_right;
       const unsigned ip = ib + pl * (unsigned)p;
       VecW<W> s2, r2;
       applyw<W>(fetch_coef(qlds[bp], tid), a.dt, c1, lft, rgt, dn1, s1_j, ym1, yp1, s2, r2);
