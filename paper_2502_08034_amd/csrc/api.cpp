@@ -252,6 +252,7 @@ struct Solver {
     a.s_in = dc ? T(0) : (T)p->s_in;
     a.s_eq = dc ? T(0) : (T)p->s_eq;
     a.Da = (T)p->Da;
+    a.gscale = T(0);
     a.pinned = pinned;
     a.lo = lo;
     a.hi = hi;
@@ -768,7 +769,25 @@ int socfv_solve_soc_adjoint(socfv_ctx *c, const socfv_params *p, double *dU_dkap
   auto adj_chunk = [&](auto *b0, auto *b1, int &cc, int k, bool dc, auto w, double gs) -> int {
     using T = std::remove_pointer_t<decltype(b0)>;
     T *b[2] = {b0, b1};
-    for (int j = 0; j < k; ++j) {
+    long long nb = S.nblk;
+    int j = 0;
+    if constexpr (std::is_same_v<T, float>) {
+      // FP32 corrections: two transpose sweeps per launch where the shape allows; an odd
+      // remainder ends with one single sweep
+      if (dc && two_path(c->g) && S.t.two) {
+        for (; j + 1 < k; j += 2) {
+          SweepArgs<float> a = S.sweep_args<float>(b[cc], b[cc ^ 1], true,
+                                                   j + 2 >= k ? c->partial : nullptr);
+          a.w = w;
+          a.gscale = (float)gs;
+          launch_sweep2(a, S.t, c->st, true);
+          cc ^= 1;
+        }
+        const dim3 g2 = sweep2_grid(c->g, S.t);
+        nb = (long long)g2.x * g2.y * g2.z;
+      }
+    }
+    for (; j < k; ++j) {
       AdjointArgs<T> a;
       a.g = c->g; a.flags = c->flags; a.w = w; a.kappa = c->kappa;
       a.psi = b[cc]; a.psi_new = b[cc ^ 1]; a.r0 = dc ? c->r0 : nullptr;
@@ -776,9 +795,10 @@ int socfv_solve_soc_adjoint(socfv_ctx *c, const socfv_params *p, double *dU_dkap
       a.partial = j == k - 1 ? c->partial : nullptr; a.zc = S.t.zc;
       launch_adjoint<T>(a, S.t, c->st);
       cc ^= 1;
+      nb = S.nblk;
     }
     HIPCHK(hipGetLastError());
-    return reduce_to_host(c, (int)S.nblk, NV, 0u, out);
+    return reduce_to_host(c, (int)nb, NV, 0u, out);
   };
   if (p->precision == SOCFV_FP64) {
     while (S.it < p->max_iter) {

@@ -38,6 +38,7 @@ struct SweepArgs {
   T *s_new;             // state (or correction) written
   const float *r0;      // defect correction: frozen FP64 residual in FP32 (else null)
   T dt, s_in, s_eq, Da; // in the correction form s_in = s_eq = 0
+  T gscale;             // transpose sweeps: g_P = gscale * w_out,P on outlet cells
   int pinned;
   double lo, hi;        // bound check on the written state (ignored for corrections)
   double *partial;      // nullable: per-block [sum R^2, violations, sum R, -]
@@ -130,7 +131,8 @@ dim3 sweep_grid_v4(const Grid &g, const Tiles &t);
 // two FP32 sweeps per launch (nx even): tiles of 124 x 14 output cells
 bool two_path(const Grid &g);
 dim3 sweep2_grid(const Grid &g, const Tiles &t);
-void launch_sweep2(const SweepArgs<float> &a, const Tiles &t, hipStream_t st);
+// adj: sweeps of the transpose system (correction form only)
+void launch_sweep2(const SweepArgs<float> &a, const Tiles &t, hipStream_t st, bool adj = false);
 
 // ---- kernels (launch wrappers; all enqueue on `st`) ---------------------------------
 

@@ -491,14 +491,19 @@ __device__ __forceinline__ float inflow_coef(float h, float w, float G) {
 }
 
 // ACT: the activity field is set and its values came with the plane's loads (a load here
-// would make the step wait for every load in flight).
-template <bool DC, bool ACT, int W>
+// would make the step wait for every load in flight).  ADJ: coefficients of the transpose
+// system A^T psi = g in the same form, r = src - psi e + sum_f b_f (psi_nb - psi): b_f takes
+// the outflow velocity through f (max(w_out, 0) + G_f), the outlet face's flux w psi_P goes
+// to the diagonal, e = lam + w_out at the outlet, and src = g_P = gscale w_out on outlet
+// cells (plus r0 for a correction).  Behind the inlet psi_nb = 0, as s_in is 0.
+template <bool DC, bool ACT, bool ADJ, int W>
 __device__ __forceinline__ void resolvew(const SweepArgs<float> &a, const CoefW<W> &c, int x,
                                          int y, int z, bool up, ResW<W> &q) {
   const int nx = a.g.nx, ny = a.g.ny;
   // walls of this row / plane as closed-face bits (y, z)
   const unsigned wall = (y > 0 ? 0u : (unsigned)FL_YM) | (y < ny - 1 ? 0u : (unsigned)FL_YP) |
                         (z > 0 ? 0u : (unsigned)FL_ZM) | (up ? 0u : (unsigned)FL_ZP);
+  const float sg = ADJ ? -1.f : 1.f;     // inflow (forward) or outflow (transpose) velocity
 #pragma unroll
   for (int k = 0; k < W; ++k) {
     const unsigned f = (c.fl >> (8 * k)) & 0xffu;
@@ -511,17 +516,23 @@ __device__ __forceinline__ void resolvew(const SweepArgs<float> &a, const CoefW<
     const float h = upd ? 0.5f : 0.f;
     const float lam = a.Da * (ACT ? c.kap.v[k] : 1.f) * (float)nf;
     const float wxm = c.wx.v[k], wxp = k == W - 1 ? c.wxr : c.wx.v[k + 1];
-    const float div = (wxp - wxm) + (c.wyp.v[k] - c.wym.v[k]) + (c.wzu.v[k] - c.wzl.v[k]);
     // inlet face: Dirichlet value on the face, G = 2 (closed bit 0 is never set there); the
-    // outlet face's flux s_P w is all in e
-    q.axm.v[k] = inflow_coef(h, wxm, gbit(closed, 0) + (upd && xk == 0 ? 1.f : 0.f));
-    q.axp.v[k] = inflow_coef(h, outlet ? 0.f : -wxp, outlet ? 0.f : gbit(closed, 1));
-    q.aym.v[k] = inflow_coef(h, c.wym.v[k], gbit(closed, 2));
-    q.ayp.v[k] = inflow_coef(h, -c.wyp.v[k], gbit(closed, 3));
-    q.azm.v[k] = inflow_coef(h, c.wzl.v[k], gbit(closed, 4));
-    q.azp.v[k] = inflow_coef(h, -c.wzu.v[k], gbit(closed, 5));
-    const float e = div + lam;
-    const float src = DC ? c.r0.v[k] : lam * a.s_eq;
+    // outlet face's flux is all on the diagonal
+    q.axm.v[k] = inflow_coef(h, sg * wxm, gbit(closed, 0) + (upd && xk == 0 ? 1.f : 0.f));
+    q.axp.v[k] = inflow_coef(h, outlet ? 0.f : -sg * wxp, outlet ? 0.f : gbit(closed, 1));
+    q.aym.v[k] = inflow_coef(h, sg * c.wym.v[k], gbit(closed, 2));
+    q.ayp.v[k] = inflow_coef(h, -sg * c.wyp.v[k], gbit(closed, 3));
+    q.azm.v[k] = inflow_coef(h, sg * c.wzl.v[k], gbit(closed, 4));
+    q.azp.v[k] = inflow_coef(h, -sg * c.wzu.v[k], gbit(closed, 5));
+    float e, src;
+    if (ADJ) {
+      e = lam + (outlet ? wxp : 0.f);
+      src = (outlet ? a.gscale * wxp : 0.f) + (DC ? c.r0.v[k] : 0.f);
+    } else {
+      const float div = (wxp - wxm) + (c.wyp.v[k] - c.wym.v[k]) + (c.wzu.v[k] - c.wzl.v[k]);
+      e = div + lam;
+      src = DC ? c.r0.v[k] : lam * a.s_eq;
+    }
     q.e.v[k] = upd ? e : 0.f;
     q.src.v[k] = upd ? src : 0.f;
   }
@@ -559,7 +570,7 @@ __device__ __forceinline__ void sweepw(const SweepArgs<float> &a, const CoefW<W>
                                        const VecW<W> &sym, const VecW<W> &syp, int x, int y,
                                        int z, bool up, VecW<W> &out, VecW<W> &rout) {
   ResW<W> q;
-  resolvew<DC, ACT, W>(a, c, x, y, z, up, q);
+  resolvew<DC, ACT, false, W>(a, c, x, y, z, up, q);
   applyw<W>(q, a.dt, sc, left, right, sdn, sup, sym, syp, out, rout);
 }
 
@@ -669,7 +680,7 @@ __device__ __forceinline__ void load_plane2(const SweepArgs<float> &a, Plane2 &d
   }
 }
 
-template <bool DC, bool RES, bool ACT>
+template <bool DC, bool RES, bool ACT, bool ADJ>
 __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int gy, int gz) {
   constexpr int W = T2_W;
   __shared__ float lds[2][T2_ROWS][64 * W];
@@ -737,7 +748,7 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
     VecW<W> r1, s1_j;
     if (j < nz) {
       ResW<W> q;
-      resolvew<DC, ACT, W>(a, cur.c, xc, yc, j, j + 1 < nz, q);
+      resolvew<DC, ACT, ADJ, W>(a, cur.c, xc, yc, j, j + 1 < nz, q);
       applyw<W>(q, a.dt, s_c, left, right, sdn, cur.s_up, cur.sym, cur.syp, s1_j, r1);
       park_coef(qlds[j & 1], tid, q);
     } else {
@@ -922,15 +933,23 @@ void with_flags(bool a, bool b, bool c, F &&f) {
   }
 }
 
-void launch_sweep2(const SweepArgs<float> &a, const Tiles &t, hipStream_t st) {
+void launch_sweep2(const SweepArgs<float> &a, const Tiles &t, hipStream_t st, bool adj) {
   dim3 gv = sweep2_grid(a.g, t);
   const unsigned nb = gv.x * gv.y * gv.z;
   SweepArgs<float> b = a;
   b.zc = t.zc2;
   dim3 block(64, T2_ROWS, 1);
+  if (adj) {
+    // transpose sweeps run only in the correction form
+    with_flags(true, a.partial != nullptr, a.kappa != nullptr, [&](auto, auto res, auto act) {
+      k_sweep2<true, res.value, act.value, true><<<nb, block, 0, st>>>(b, gv.x, gv.y, gv.z);
+    });
+    return;
+  }
   with_flags(a.r0 != nullptr, a.partial != nullptr, a.kappa != nullptr,
              [&](auto dc, auto res, auto act) {
-               k_sweep2<dc.value, res.value, act.value><<<nb, block, 0, st>>>(b, gv.x, gv.y, gv.z);
+               k_sweep2<dc.value, res.value, act.value, false><<<nb, block, 0, st>>>(b, gv.x,
+                                                                                    gv.y, gv.z);
              });
 }
 

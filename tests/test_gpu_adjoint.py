@@ -49,6 +49,38 @@ def test_adjoint_matches_oracle(sv, orc, shape, prec):
     assert abs(dlnq - dlnqx) <= tol * abs(dlnqx)
 
 
+@pytest.mark.parametrize("pinned", [False, True])
+def test_adjoint_two_sweep_launches_match_oracle(sv, orc, pinned):
+    """FP32-mode adjoint with one and with two transpose sweeps per launch (shape 128 x 40 x
+    33: several tiles, ragged in y and z), each against the oracle's exact adjoint; held and
+    fibre cells keep psi = 0."""
+    solid, u = case(128, 40, 33, seed=45)
+    kappa = None if pinned else I.lognormal_activity(solid, 0.3, seed=8)
+    pb = sv.Problem.create(solid, *u, kappa=kappa)
+    kw = dict(mode=1, s_in=0.0, s_eq=1.0, Da=0.0) if pinned else {}
+    p = sv.params(precision="fp32", tol=1e-10, check_every=100, **kw)
+    sv.solve_soc_steady(pb.ctx, p)
+    if pinned:
+        op = orc.Problem(solid, *u, s_in=0.0, s_eq=1.0, pinned=True)
+    else:
+        op = orc.Problem(solid, *u, s_in=1.0, s_eq=0.0, Da=0.45, kappa=kappa.astype(np.float64))
+    sx = orc.exact_steady(op)
+    px = orc.exact_adjoint(op)
+    gx, dlnqx = orc.gradients(op, sx, px)
+    held = (op.nf > 0) & (solid == 0) if pinned else np.zeros(solid.shape, bool)
+    for two in (0, 1):
+        sv.set_tiles(pb.ctx, 0, 0, 0, two)
+        g, dlnq, psi, st = sv.solve_soc_adjoint(pb.ctx, p, want_psi=True)
+        assert st.status == sv.OK
+        pn = psi.cpu().numpy()
+        # the oracle also defines psi on held cells (after the solve); the library keeps 0
+        assert np.abs(pn - px)[~held].max() <= 1e-5 * np.abs(px).max(), two
+        assert abs(dlnq - dlnqx) <= 1e-5 * abs(dlnqx), two
+        if not pinned:
+            assert np.abs(g.cpu().numpy() - gx).max() <= 1e-5 * np.abs(gx).max(), two
+        assert np.all(pn[solid == 1] == 0.0) and np.all(pn[held] == 0.0)
+
+
 def test_adjoint_pinned_mode(sv, orc):
     solid, u = case(64, 32, 32, seed=42)
     pb = sv.Problem.create(solid, *u)
