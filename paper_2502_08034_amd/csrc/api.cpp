@@ -93,11 +93,13 @@ Faces<float> faces32(const socfv_ctx *c) { return {c->w32[0], c->w32[1], c->w32[
 Faces<double> faces64(const socfv_ctx *c) { return {c->w64[0], c->w64[1], c->w64[2], c->w64[3]}; }
 
 // Two-sweep launches run one block per CU (its LDS and registers fill a CU), each block
-// marching one 124 x 14 output tile through a z chunk plus two extra planes.  The chunk
+// marching one (62 W) x 14 output tile (W cells per lane) through a z chunk plus two extra
+// planes.  The chunk
 // count is chosen to minimise (rounds of blocks over the CUs) x (planes per block), with
 // chunks of at least 8 planes unless nz is smaller.
 int pick_zc2(const Grid &g, int ncu) {
-  const long long t2 = (long long)((g.nx + 123) / 124) * ((g.ny + 13) / 14);
+  const int ox = 62 * two_w(g);
+  const long long t2 = (long long)((g.nx + ox - 1) / ox) * ((g.ny + 13) / 14);
   if (ncu < 1) ncu = 1;
   long long best = -1;
   int zbest = g.nz;
@@ -1051,7 +1053,44 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
       launch_fill_f32(c->s32[1], c->g.n, 0.0f, bs);
       if (res[i] < p[i].tol) { done[i] = 1; status[i] = SOCFV_OK; }
     }
-    // tiles: one block shape for the batch, picked by timing a few sweeps per candidate
+    // Problems whose shape allows it (nx even; no activity field in the batch) take two
+    // sweeps per launch in the batched two-sweep kernel; the others take the batched
+    // single-sweep kernel.  Its block shape is picked by timing a few sweeps per candidate;
+    // the two-sweep z chunk comes from the same rounds x planes cost model as one problem's.
+    bool any_kappa = false;
+    for (int i = 0; i < n; ++i) any_kappa = any_kappa || ctxs[i]->kappa != nullptr;
+    std::vector<int> two(n, 0);
+    int n_two = 0;
+    for (int i = 0; i < n; ++i) {
+      two[i] = !any_kappa && two_path(ctxs[i]->g) && ctxs[i]->tiles.two;
+      n_two += two[i];
+    }
+    int dev = 0, ncu = 256;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    // z chunk of the two-sweep items for the problems still running (act): the rounds x
+    // planes cost model over their items; re-picked whenever a problem finishes, so that the
+    // last problems of a batch still spread over the chip
+    auto pick_zc2 = [&](const std::vector<int> &act) {
+      long long best_cost = -1;
+      int zbest = 8, zmax = 8;
+      for (int i = 0; i < n; ++i)
+        if (two[i] && act[i]) zmax = std::max(zmax, ctxs[i]->g.nz);
+      for (int z = 8; z <= zmax; ++z) {
+        long long items = 0;
+        for (int i = 0; i < n; ++i) {
+          if (!two[i] || !act[i]) continue;
+          const Grid &g = ctxs[i]->g;
+          const int zz = std::min(z, g.nz);
+          const int ox = 62 * two_w(g);
+          items += (long long)((g.nx + ox - 1) / ox) * ((g.ny + 13) / 14) * ((g.nz + zz - 1) / zz);
+        }
+        const long long cost = (items + ncu - 1) / ncu * (z + 2);
+        if (best_cost < 0 || cost < best_cost) { best_cost = cost; zbest = z; }
+      }
+      return zbest;
+    };
+    int zc2 = pick_zc2(std::vector<int>(n, 1));
     auto build = [&](int ty, int zc, std::vector<BatchProb> &hp, std::vector<int> &tp) {
       hp.assign(n, BatchProb{});
       tp.clear();
@@ -1066,47 +1105,70 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
         b.r0 = c->r0;
         b.dt = (float)S[i].dt; b.Da = (float)p[i].Da; b.s_in = (float)p[i].s_in;
         b.s_eq = (float)p[i].s_eq; b.lo = S[i].lo; b.hi = S[i].hi; b.pinned = S[i].pinned;
-        b.gx = (c->g.nx + 63) / 64; b.gy = (c->g.ny + ty - 1) / ty;
-        b.zc = std::min(zc, c->g.nz);
+        if (two[i]) {
+          const int ox = 62 * two_w(c->g);
+          b.gx = (c->g.nx + ox - 1) / ox; b.gy = (c->g.ny + 13) / 14;
+          b.zc = std::min(zc2, c->g.nz);
+        } else {
+          b.gx = (c->g.nx + 63) / 64; b.gy = (c->g.ny + ty - 1) / ty;
+          b.zc = std::min(zc, c->g.nz);
+        }
         b.gz = (c->g.nz + b.zc - 1) / b.zc;
         b.tile0 = (int)tp.size();
         for (int t = 0; t < b.gx * b.gy * b.gz; ++t) tp.push_back(i);
       }
     };
-    int dev = 0, ncu = 256;
-    HIPCHK(hipGetDevice(&dev));
-    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     std::vector<BatchProb> hp;
     std::vector<int> tp;
     size_t max_tiles = 0;
     const int tys[] = {2, 4, 8};
     const int zcs[] = {2, 4, 8, 16};
-    for (int ty : tys)
-      for (int zc : zcs) {
-        build(ty, zc, hp, tp);
-        max_tiles = std::max(max_tiles, tp.size());
-      }
+    {
+      // buffers for every tiling used below: any candidate shape, two-sweep chunks down to 8
+      const int zc2_run = zc2;
+      for (int z2 : {8, zc2_run})
+        for (int ty : tys)
+          for (int zc : zcs) {
+            zc2 = z2;
+            build(ty, zc, hp, tp);
+            max_tiles = std::max(max_tiles, tp.size());
+          }
+      zc2 = zc2_run;
+    }
     HIPCHK(hipMalloc(&d_probs, sizeof(BatchProb) * n));
     HIPCHK(hipMalloc(&d_tiles, sizeof(int) * max_tiles));
-    HIPCHK(hipMalloc(&d_work, sizeof(int) * max_tiles));
-    HIPCHK(hipMalloc(&d_nwork, sizeof(int)));
+    // work lists: two-sweep items at d_work, single-sweep items at d_work + max_tiles;
+    // their counts at d_nwork[0] and d_nwork[1]
+    HIPCHK(hipMalloc(&d_work, sizeof(int) * 2 * max_tiles));
+    HIPCHK(hipMalloc(&d_nwork, sizeof(int) * 2));
     HIPCHK(hipMalloc(&d_part, sizeof(double) * NV * max_tiles));
     HIPCHK(hipMalloc(&d_out, sizeof(double) * NV * n));
-    HIPCHK(hipHostMalloc(&h_work, sizeof(int) * (max_tiles + 1), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(&h_work, sizeof(int) * (2 * max_tiles + 2), hipHostMallocDefault));
     HIPCHK(hipHostMalloc(&h_out, sizeof(double) * NV * n, hipHostMallocDefault));
-    // work list = every tile of the unfinished problems (count at h_work[0])
+    // work lists = every tile of the unfinished problems, by path (counts at h_work[0..1])
     auto upload_work = [&](const std::vector<BatchProb> &hp_, const std::vector<int> &done_) -> int {
-      int m = 0;
+      int m[2] = {0, 0};
+      int *lst[2] = {h_work + 2, h_work + 2 + max_tiles};
       for (int i = 0; i < n; ++i) {
         if (done_[i]) continue;
+        const int k = two[i] ? 0 : 1;
         const int nt = hp_[i].gx * hp_[i].gy * hp_[i].gz;
-        for (int t = 0; t < nt; ++t) h_work[1 + m++] = hp_[i].tile0 + t;
+        for (int t = 0; t < nt; ++t) lst[k][m[k]++] = hp_[i].tile0 + t;
       }
-      h_work[0] = m;
-      HIPCHK(hipMemcpyAsync(d_nwork, h_work, sizeof(int), hipMemcpyHostToDevice, bs));
-      if (m) HIPCHK(hipMemcpyAsync(d_work, h_work + 1, sizeof(int) * m, hipMemcpyHostToDevice, bs));
+      h_work[0] = m[0];
+      h_work[1] = m[1];
+      HIPCHK(hipMemcpyAsync(d_nwork, h_work, sizeof(int) * 2, hipMemcpyHostToDevice, bs));
+      for (int k = 0; k < 2; ++k)
+        if (m[k])
+          HIPCHK(hipMemcpyAsync(d_work + k * max_tiles, lst[k], sizeof(int) * m[k],
+                                hipMemcpyHostToDevice, bs));
       HIPCHK(hipStreamSynchronize(bs));   // h_work is rewritten by the next upload
       return 0;
+    };
+    int n_one_tiles = 0, n_two_tiles = 0;
+    auto count_tiles = [&](const std::vector<BatchProb> &hp_) {
+      n_one_tiles = n_two_tiles = 0;
+      for (int i = 0; i < n; ++i) (two[i] ? n_two_tiles : n_one_tiles) += hp_[i].gx * hp_[i].gy * hp_[i].gz;
     };
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -1121,17 +1183,21 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
     };
     for (int ty : tys)
       for (int zc : zcs) {
+        if (n_two == n) break;   // no single-sweep problems to time
         build(ty, zc, hp, tp);
+        count_tiles(hp);
         HIPCHK(hipMemcpyAsync(d_probs, hp.data(), sizeof(BatchProb) * n, hipMemcpyHostToDevice, bs));
         HIPCHK(hipMemcpyAsync(d_tiles, tp.data(), sizeof(int) * tp.size(), hipMemcpyHostToDevice, bs));
         std::vector<int> none(n, 0);
         TRY(upload_work(hp, none));
-        const int nb = nblocks_for(ty, tp.size());
+        const int nb = nblocks_for(ty, n_one_tiles);
         // timing sweeps change the correction buffers: they are cleared again below
-        launch_batch_sweep(d_probs, d_tiles, d_work, d_nwork, nb, ty, 0, true, nullptr, bs);
+        launch_batch_sweep(d_probs, d_tiles, d_work + max_tiles, d_nwork + 1, nb, ty, 0, true,
+                           nullptr, bs);
         HIPCHK(hipEventRecord(e0, bs));
         for (int j = 0; j < 4; ++j)
-          launch_batch_sweep(d_probs, d_tiles, d_work, d_nwork, nb, ty, j & 1, true, nullptr, bs);
+          launch_batch_sweep(d_probs, d_tiles, d_work + max_tiles, d_nwork + 1, nb, ty, j & 1,
+                             true, nullptr, bs);
         HIPCHK(hipEventRecord(e1, bs));
         HIPCHK(hipEventSynchronize(e1));
         HIPCHK(hipGetLastError());
@@ -1142,8 +1208,10 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     build(bty, bzc, hp, tp);
+    count_tiles(hp);
     const int ntiles = (int)tp.size();
-    const int nb = nblocks_for(bty, tp.size());
+    const int nb = nblocks_for(bty, std::max(n_one_tiles, 1));
+    const int nb2 = ncu;        // persistent two-sweep blocks (items may grow on re-tiling)
     HIPCHK(hipMemcpyAsync(d_probs, hp.data(), sizeof(BatchProb) * n, hipMemcpyHostToDevice, bs));
     HIPCHK(hipMemcpyAsync(d_tiles, tp.data(), sizeof(int) * ntiles, hipMemcpyHostToDevice, bs));
     TRY(upload_work(hp, done));
@@ -1151,14 +1219,27 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
       launch_fill_f32(ctxs[i]->s32[0], ctxs[i]->g.n, 0.0f, bs);
       launch_fill_f32(ctxs[i]->s32[1], ctxs[i]->g.n, 0.0f, bs);
     }
-    // capture one chunk: K sweeps (parity 0, 1, ...), partials on the last, per-problem sums
-    int K = 2;
+    // capture one chunk of K sweeps, K a multiple of 4: per pair of sweeps one two-sweep
+    // launch (its buffers flip once) and two single-sweep launches (theirs flip twice), so
+    // after K sweeps every problem's correction is back in s32[0]; partials on the last
+    // launches, then per-problem sums
+    int K = 4;
     for (int i = 0; i < n; ++i) K = std::max(K, S[i].chunk_len());
+    K = (K + 3) / 4 * 4;
     HIPCHK(hipStreamSynchronize(bs));
     HIPCHK(hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal));
-    for (int j = 0; j < K; ++j)
-      launch_batch_sweep(d_probs, d_tiles, d_work, d_nwork, nb, bty, j & 1, true,
-                         j == K - 1 ? d_part : nullptr, bs);
+    for (int j = 0; j < K / 2; ++j) {
+      const bool lastp = j == K / 2 - 1;
+      if (n_two_tiles)
+        launch_batch_sweep2(d_probs, d_tiles, d_work, d_nwork, nb2, j & 1,
+                            lastp ? d_part : nullptr, bs);
+      if (n_one_tiles) {
+        launch_batch_sweep(d_probs, d_tiles, d_work + max_tiles, d_nwork + 1, nb, bty, 0, true,
+                           nullptr, bs);
+        launch_batch_sweep(d_probs, d_tiles, d_work + max_tiles, d_nwork + 1, nb, bty, 1, true,
+                           lastp ? d_part : nullptr, bs);
+      }
+    }
     launch_batch_reduce(d_probs, n, d_part, d_out, bs);
     HIPCHK(hipStreamEndCapture(bs, &graph));
     HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
@@ -1169,6 +1250,23 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
       for (int i = 0; i < n; ++i) nact += !done[i];
       if (!nact) break;
       if (changed) {
+        // fewer problems left: shorter chunks for more items; single-sweep chunks halved
+        // while their items are fewer than the persistent blocks
+        std::vector<int> act(n);
+        for (int i = 0; i < n; ++i) act[i] = !done[i];
+        zc2 = pick_zc2(act);
+        auto tiles1 = [&](int zc) {
+          long long m = 0;
+          for (int i = 0; i < n; ++i)
+            if (act[i] && !two[i])
+              m += (long long)((ctxs[i]->g.nx + 63) / 64) * ((ctxs[i]->g.ny + bty - 1) / bty) *
+                   ((ctxs[i]->g.nz + std::min(zc, ctxs[i]->g.nz) - 1) / std::min(zc, ctxs[i]->g.nz));
+          return m;
+        };
+        while (bzc > 2 && tiles1(bzc) < nb) bzc /= 2;
+        build(bty, bzc, hp, tp);
+        HIPCHK(hipMemcpyAsync(d_probs, hp.data(), sizeof(BatchProb) * n, hipMemcpyHostToDevice, bs));
+        HIPCHK(hipMemcpyAsync(d_tiles, tp.data(), sizeof(int) * tp.size(), hipMemcpyHostToDevice, bs));
         TRY(upload_work(hp, done));
         changed = false;
       }

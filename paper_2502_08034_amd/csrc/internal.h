@@ -105,7 +105,8 @@ struct BatchProb {
   float dt, Da, s_in, s_eq;
   double lo, hi;
   int pinned;
-  int gx, gy, gz, zc;   // tile grid of this problem (64 x ty lanes, zc planes)
+  int gx, gy, gz, zc;   // tile grid of this problem: 64 x ty lanes x zc planes, or for the
+                        // two-sweep path 124 x 14 output cells x zc planes
   int tile0;            // index of its first tile in the work list
 };
 
@@ -113,6 +114,11 @@ struct BatchProb {
 void launch_batch_sweep(const BatchProb *probs, const int *tile_prob, const int *work,
                         const int *nwork, int nblocks, int ty, int parity, bool dc,
                         double *partial, hipStream_t st);
+// two sweeps per launch over the work list's (problem, tile) items; correction form, no
+// activity field
+void launch_batch_sweep2(const BatchProb *probs, const int *tile_prob, const int *work,
+                         const int *nwork, int nblocks, int parity, double *partial,
+                         hipStream_t st);
 void launch_batch_reduce(const BatchProb *probs, int n, const double *partial, double *out,
                          hipStream_t st);
 
@@ -130,6 +136,7 @@ bool vec4_path(const Grid &g);
 dim3 sweep_grid_v4(const Grid &g, const Tiles &t);
 // two FP32 sweeps per launch (nx even): tiles of 124 x 14 output cells
 bool two_path(const Grid &g);
+int two_w(const Grid &g);   // cells per lane of the two-sweep kernel: 2 for even nx, 1 for odd
 dim3 sweep2_grid(const Grid &g, const Tiles &t);
 // adj: sweeps of the transpose system (correction form only)
 void launch_sweep2(const SweepArgs<float> &a, const Tiles &t, hipStream_t st, bool adj = false);

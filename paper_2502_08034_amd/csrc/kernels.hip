@@ -411,48 +411,63 @@ template <bool DC, bool RES, bool ACT>
 __global__ void __launch_bounds__(1024) k_sweep_v4(SweepArgs<float> a, int gx, int gy, int gz);
 
 // Two sweeps per launch (time skewing along the z march).  A block of 64 x 16 lanes holds
-// a (64 W) x 16 tile, W consecutive x cells per lane, and writes the second sweep on its
-// interior (62 W) x 14 cells; tiles overlap by one lane in x and one row in y on each side,
-// where the first sweep is recomputed.  Marching plane j, the block computes the first
-// sweep s1(j) from s(j-1..j+1) over the whole tile, stages s1(j) in LDS (three plane
-// buffers, one barrier per plane), and the second sweep at plane j-1 from s1(j-2..j): the
-// own column from registers, x and y neighbours from LDS.  State, velocities, flags and
-// the frozen residual come from HBM once for two sweeps.  Each sweep is the arithmetic of
-// one k_sweep_v4 sweep, cell by cell.
-constexpr int T2_ROWS = 16, T2_W = 2, T2_OUT_X = 62 * T2_W, T2_OUT_Y = 14;
+// a (64 W) x 16 tile, W consecutive x cells per lane (W = 2 for even nx, 1 for odd), and
+// writes the second sweep on its interior (62 W) x 14 cells; tiles overlap by one lane in x
+// and one row in y on each side, where the first sweep is recomputed.  Marching plane j,
+// the block computes the first sweep s1(j) from s(j-1..j+1) over the whole tile, stages
+// s1(j) in LDS (two plane slots, one barrier per plane), and the second sweep at plane j-1
+// from s1(j-2..j).  State, velocities, flags and the frozen residual come from HBM once for
+// two sweeps.  Each sweep is the arithmetic of one k_sweep_v4 sweep, cell by cell.
+constexpr int T2_ROWS = 16, T2_OUT_Y = 14;
 
 template <int W>
 struct VecW {
   float v[W];
 };
 
+// Device-memory accesses through global-address-space pointers.  Array pointers read from a
+// table in memory (the batched kernels) would otherwise be generic, and the compiler would
+// emit flat accesses, which also count against the LDS wait counter and so make every LDS
+// wait of a step wait for the loads in flight as well.
+#define GMEM __attribute__((address_space(1)))
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
 template <int W>
 __device__ __forceinline__ VecW<W> ldw(const float *p) {
   VecW<W> r;
   if constexpr (W == 4) {
-    float4 t = *(const float4 *)p;
+    const f4v t = *(GMEM const f4v *)p;
     r.v[0] = t.x; r.v[1] = t.y; r.v[2] = t.z; r.v[3] = t.w;
   } else if constexpr (W == 2) {
-    float2 t = *(const float2 *)p;
+    const f2v t = *(GMEM const f2v *)p;
     r.v[0] = t.x; r.v[1] = t.y;
   } else {
-    r.v[0] = *p;
+    r.v[0] = *(GMEM const float *)p;
   }
   return r;
 }
 
 template <int W>
 __device__ __forceinline__ void stw(float *p, const VecW<W> &r) {
-  if constexpr (W == 4) *(float4 *)p = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
-  else if constexpr (W == 2) *(float2 *)p = make_float2(r.v[0], r.v[1]);
-  else *p = r.v[0];
+  if constexpr (W == 4) {
+    f4v t;
+    t.x = r.v[0]; t.y = r.v[1]; t.z = r.v[2]; t.w = r.v[3];
+    *(GMEM f4v *)p = t;
+  } else if constexpr (W == 2) {
+    f2v t;
+    t.x = r.v[0]; t.y = r.v[1];
+    *(GMEM f2v *)p = t;
+  } else {
+    *(GMEM float *)p = r.v[0];
+  }
 }
 
 template <int W>
 __device__ __forceinline__ unsigned ldflags(const uint8_t *p) {
-  if constexpr (W == 4) return *(const unsigned *)p;
-  else if constexpr (W == 2) return *(const unsigned short *)p;
-  else return *p;
+  if constexpr (W == 4) return *(GMEM const unsigned *)p;
+  else if constexpr (W == 2) return *(GMEM const unsigned short *)p;
+  else return *(GMEM const uint8_t *)p;
 }
 
 template <int W>
@@ -574,11 +589,12 @@ __device__ __forceinline__ void sweepw(const SweepArgs<float> &a, const CoefW<W>
   applyw<W>(q, a.dt, sc, left, right, sdn, sup, sym, syp, out, rout);
 }
 
-// Everything a lane (two cells) reads from plane j: the state one plane up, the state of
+// Everything a lane (W cells) reads from plane j: the state one plane up, the state of
 // rows y-1 / y+1, the coefficients, and the x-edge values its wave's edge lanes need.
-struct Plane2 {
-  VecW<2> s_up, sym, syp;
-  CoefW<2> c;
+template <int W>
+struct PlaneW {
+  VecW<W> s_up, sym, syp;
+  CoefW<W> c;
   float left, right;
 };
 
@@ -595,41 +611,57 @@ __device__ __forceinline__ float lane_from_above(float v) {
                                                                0x130, 0xf, 0xf, false));
 }
 
-// A lane's resolved coefficients (two cells) parked in LDS between its two sweeps of a
-// plane: four float4 per lane, lane-private (no barrier needed), two plane slots.
-__device__ __forceinline__ void park_coef(float4 (*slot)[64 * T2_ROWS], int t, const ResW<2> &q) {
-  slot[0][t] = make_float4(q.axm.v[0], q.axm.v[1], q.axp.v[0], q.axp.v[1]);
-  slot[1][t] = make_float4(q.aym.v[0], q.aym.v[1], q.ayp.v[0], q.ayp.v[1]);
-  slot[2][t] = make_float4(q.azm.v[0], q.azm.v[1], q.azp.v[0], q.azp.v[1]);
-  slot[3][t] = make_float4(q.e.v[0], q.e.v[1], q.src.v[0], q.src.v[1]);
+// A lane's resolved coefficients (W cells, 8 W floats) parked in LDS between its two sweeps
+// of a plane: 2 W float4 per lane, lane-private (no barrier needed), two plane slots.
+template <int W>
+__device__ __forceinline__ void park_coef(float4 (*slot)[64 * T2_ROWS], int t, const ResW<W> &q) {
+  if constexpr (W == 2) {
+    slot[0][t] = make_float4(q.axm.v[0], q.axm.v[1], q.axp.v[0], q.axp.v[1]);
+    slot[1][t] = make_float4(q.aym.v[0], q.aym.v[1], q.ayp.v[0], q.ayp.v[1]);
+    slot[2][t] = make_float4(q.azm.v[0], q.azm.v[1], q.azp.v[0], q.azp.v[1]);
+    slot[3][t] = make_float4(q.e.v[0], q.e.v[1], q.src.v[0], q.src.v[1]);
+  } else {
+    slot[0][t] = make_float4(q.axm.v[0], q.axp.v[0], q.aym.v[0], q.ayp.v[0]);
+    slot[1][t] = make_float4(q.azm.v[0], q.azp.v[0], q.e.v[0], q.src.v[0]);
+  }
 }
 
-__device__ __forceinline__ ResW<2> fetch_coef(float4 (*slot)[64 * T2_ROWS], int t) {
-  ResW<2> q;
-  float4 v = slot[0][t];
-  q.axm.v[0] = v.x; q.axm.v[1] = v.y; q.axp.v[0] = v.z; q.axp.v[1] = v.w;
-  v = slot[1][t];
-  q.aym.v[0] = v.x; q.aym.v[1] = v.y; q.ayp.v[0] = v.z; q.ayp.v[1] = v.w;
-  v = slot[2][t];
-  q.azm.v[0] = v.x; q.azm.v[1] = v.y; q.azp.v[0] = v.z; q.azp.v[1] = v.w;
-  v = slot[3][t];
-  q.e.v[0] = v.x; q.e.v[1] = v.y; q.src.v[0] = v.z; q.src.v[1] = v.w;
+template <int W>
+__device__ __forceinline__ ResW<W> fetch_coef(float4 (*slot)[64 * T2_ROWS], int t) {
+  ResW<W> q;
+  if constexpr (W == 2) {
+    float4 v = slot[0][t];
+    q.axm.v[0] = v.x; q.axm.v[1] = v.y; q.axp.v[0] = v.z; q.axp.v[1] = v.w;
+    v = slot[1][t];
+    q.aym.v[0] = v.x; q.aym.v[1] = v.y; q.ayp.v[0] = v.z; q.ayp.v[1] = v.w;
+    v = slot[2][t];
+    q.azm.v[0] = v.x; q.azm.v[1] = v.y; q.azp.v[0] = v.z; q.azp.v[1] = v.w;
+    v = slot[3][t];
+    q.e.v[0] = v.x; q.e.v[1] = v.y; q.src.v[0] = v.z; q.src.v[1] = v.w;
+  } else {
+    float4 v = slot[0][t];
+    q.axm.v[0] = v.x; q.axp.v[0] = v.y; q.aym.v[0] = v.z; q.ayp.v[0] = v.w;
+    v = slot[1][t];
+    q.azm.v[0] = v.x; q.azp.v[0] = v.y; q.e.v[0] = v.z; q.src.v[0] = v.w;
+  }
   return q;
 }
 
 // Loads and stores at a 32-bit byte offset from a kernel-argument base: the compiler then
 // addresses with the scalar base plus one 32-bit VGPR offset per lane, with no 64-bit
 // address arithmetic per access.  Every FP32 array of the two-sweep path is below 4 GiB.
-__device__ __forceinline__ VecW<2> ldo2(const float *base, unsigned off) {
-  return ldw<2>(reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + off));
+template <int W>
+__device__ __forceinline__ VecW<W> ldo(const float *base, unsigned off) {
+  return ldw<W>(reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + off));
 }
 
 __device__ __forceinline__ float ldo1(const float *base, unsigned off) {
-  return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + off);
+  return ldw<1>(reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + off)).v[0];
 }
 
-__device__ __forceinline__ void sto2(float *base, unsigned off, const VecW<2> &v) {
-  stw<2>(reinterpret_cast<float *>(reinterpret_cast<char *>(base) + off), v);
+template <int W>
+__device__ __forceinline__ void sto(float *base, unsigned off, const VecW<W> &v) {
+  stw<W>(reinterpret_cast<float *>(reinterpret_cast<char *>(base) + off), v);
 }
 
 // Loads at clamped 32-bit offsets (every address valid; out-of-range planes, rows and
@@ -637,8 +669,8 @@ __device__ __forceinline__ void sto2(float *base, unsigned off, const VecW<2> &v
 // then selects for the wall velocities that must be zero.  With UPZ the plane's upper
 // z-face velocity is loaded too; without, the caller takes it from the next plane's lower
 // face.
-template <bool DC, bool UPZ, bool ACT>
-__device__ __forceinline__ void load_plane2(const SweepArgs<float> &a, Plane2 &d,
+template <bool DC, bool UPZ, bool ACT, int W>
+__device__ __forceinline__ void load_plane2(const SweepArgs<float> &a, PlaneW<W> &d,
                                             unsigned ib, unsigned pl, int j, int xc, int yc,
                                             int lane, bool last, bool yl, bool yr) {
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
@@ -651,47 +683,44 @@ __device__ __forceinline__ void load_plane2(const SweepArgs<float> &a, Plane2 &d
   const unsigned oym = o4 - (yl ? 4u * (unsigned)nx : 0u);
   // the lower z face first: the step before this plane's reads it as its upper face, and
   // load counters complete in issue order
-  d.c.wzl = ldo2(a.w.wz, o4);
-  d.s_up = ldo2(a.s, oup);
-  d.sym = ldo2(a.s, oym);
-  d.syp = ldo2(a.s, oyp);
-  d.c.wx = ldo2(a.w.wx, o4);
-  d.c.wym = ldo2(a.w.wy, o4);
-  const VecW<2> wyp = ldo2(a.w.wy, oyp);
+  d.c.wzl = ldo<W>(a.w.wz, o4);
+  d.s_up = ldo<W>(a.s, oup);
+  d.sym = ldo<W>(a.s, oym);
+  d.syp = ldo<W>(a.s, oyp);
+  d.c.wx = ldo<W>(a.w.wx, o4);
+  d.c.wym = ldo<W>(a.w.wy, o4);
+  const VecW<W> wyp = ldo<W>(a.w.wy, oyp);
   if (UPZ) {
-    const VecW<2> wzu = ldo2(a.w.wz, oup);
+    const VecW<W> wzu = ldo<W>(a.w.wz, oup);
 #pragma unroll
-    for (int k = 0; k < 2; ++k) d.c.wzu.v[k] = up ? wzu.v[k] : 0.f;
+    for (int k = 0; k < W; ++k) d.c.wzu.v[k] = up ? wzu.v[k] : 0.f;
   }
 #pragma unroll
-  for (int k = 0; k < 2; ++k) d.c.wyp.v[k] = yr ? wyp.v[k] : 0.f;
-  d.c.fl = ldflags<2>(a.flags + o);
-  if (DC) d.c.r0 = ldo2(a.r0, o4);
-  else d.c.r0 = zerow<2>();
-  if (ACT) d.c.kap = ldo2(a.kappa, o4);
+  for (int k = 0; k < W; ++k) d.c.wyp.v[k] = yr ? wyp.v[k] : 0.f;
+  d.c.fl = ldflags<W>(a.flags + o);
+  if (DC) d.c.r0 = ldo<W>(a.r0, o4);
+  else d.c.r0 = zerow<W>();
+  if (ACT) d.c.kap = ldo<W>(a.kappa, o4);
   d.left = a.s_in;
   d.right = 0.f;
   d.c.wxr = 0.f;
   if (lane == 0 && xc > 0) d.left = ldo1(a.s, o4 - 4u);
   if (last) d.c.wxr = ldo1(a.w.wxo, 4u * (yc + (unsigned)ny * (unsigned)jj));
   else if (lane == 63) {
-    d.right = ldo1(a.s, o4 + 8u);
-    d.c.wxr = ldo1(a.w.wx, o4 + 8u);
+    d.right = ldo1(a.s, o4 + 4u * W);
+    d.c.wxr = ldo1(a.w.wx, o4 + 4u * W);
   }
 }
 
-template <bool DC, bool RES, bool ACT, bool ADJ>
-__global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int gy, int gz) {
-  constexpr int W = T2_W;
-  __shared__ float lds[2][T2_ROWS][64 * W];
-  __shared__ float4 qlds[2][4][64 * T2_ROWS];
+template <bool DC, bool RES, bool ACT, bool ADJ, int W>
+__device__ __forceinline__ void sweep2_tile(const SweepArgs<float> &a, int gx, int gy, int L,
+                                            float (*lds)[T2_ROWS][64 * W],
+                                            float4 (*qlds)[2 * W][64 * T2_ROWS], double *part) {
   const Grid g = a.g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const int nb = gx * gy * gz;
-  const int L = xcd_tile(blockIdx.x, nb);
   const int bx = L % gx, by = (L / gx) % gy, bz = L / (gx * gy);
   const int lane = threadIdx.x, row = threadIdx.y, tid = lane + 64 * row;
-  const int x = bx * T2_OUT_X - W + W * lane;
+  const int x = bx * (62 * W) - W + W * lane;
   const int y = by * T2_OUT_Y - 1 + row;
   const int z0 = bz * a.zc;
   const int z1 = min(z0 + a.zc, nz);
@@ -709,25 +738,26 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
   // copy of s1(j-1) staged in the previous step, stage s1(j).  Plane data sit in a ring of
   // four: j is swept, j-1 keeps s(j) (its s_up), and the loads of the next PD planes are in
   // flight (two ahead; one in the variant that also accumulates the residual, whose extra
-  // registers would not fit two).  First-sweep results sit in a ring of four; the loop is
-  // unrolled by four so every ring index is a compile-time constant.
+  // registers would not fit two).  The loop is unrolled by four so every ring index is a
+  // compile-time constant.
   constexpr int PD = RES || ACT ? 1 : 2;
   const int jb = max(z0 - 1, 0);
   const int je = min(z1, nz);            // inclusive; j == nz only finishes plane nz-1
-  Plane2 P[4];
+  PlaneW<W> P[4];
   VecW<W> sdn;                           // s(j-1)
   // first-sweep planes below the box are closed walls: their LDS copy must be finite
 #pragma unroll
   for (int k = 0; k < W; ++k) lds[0][row][W * lane + k] = lds[1][row][W * lane + k] = 0.f;
   {
     const unsigned o = ib + pl * (unsigned)jb;
-    sdn = jb > 0 ? ldo2(a.s, 4u * (o - pl)) : zw;
-    P[3].s_up = ldo2(a.s, 4u * o);       // s(jb)
+    sdn = jb > 0 ? ldo<W>(a.s, 4u * (o - pl)) : zw;
+    P[3].s_up = ldo<W>(a.s, 4u * o);     // s(jb)
     P[3].c.fl = 0u;
     load_plane2<DC, PD == 1, ACT>(a, P[0], ib, pl, jb, xc, yc, lane, last, yl, yr);
     if (PD == 2) load_plane2<DC, false, ACT>(a, P[1], ib, pl, jb + 1, xc, yc, lane, last, yl, yr);
   }
-  auto step = [&](Plane2 &cur, const Plane2 &prev, const Plane2 &nxt, Plane2 &ld, int j) {
+  auto step = [&](PlaneW<W> &cur, const PlaneW<W> &prev, const PlaneW<W> &nxt, PlaneW<W> &ld,
+                  int j) {
     load_plane2<DC, PD == 1, ACT>(a, ld, ib, pl, j + PD, xc, yc, lane, last, yl, yr);
     if (PD == 2) {
       // upper z face of plane j = lower z face of plane j+1 (closed above the top plane)
@@ -750,7 +780,7 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
       ResW<W> q;
       resolvew<DC, ACT, ADJ, W>(a, cur.c, xc, yc, j, j + 1 < nz, q);
       applyw<W>(q, a.dt, s_c, left, right, sdn, cur.s_up, cur.sym, cur.syp, s1_j, r1);
-      park_coef(qlds[j & 1], tid, q);
+      park_coef<W>(qlds[j & 1], tid, q);
     } else {
       s1_j = zw;
     }
@@ -779,8 +809,8 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
       const float rgt = c1_right;
       const unsigned ip = ib + pl * (unsigned)p;
       VecW<W> s2, r2;
-      applyw<W>(fetch_coef(qlds[bp], tid), a.dt, c1, lft, rgt, dn1, s1_j, ym1, yp1, s2, r2);
-      sto2(a.s_new, 4u * ip, s2);
+      applyw<W>(fetch_coef<W>(qlds[bp], tid), a.dt, c1, lft, rgt, dn1, s1_j, ym1, yp1, s2, r2);
+      sto<W>(a.s_new, 4u * ip, s2);
       if (RES) {
 #pragma unroll
         for (int k = 0; k < W; ++k) {
@@ -811,7 +841,17 @@ __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int
     if (j + 3 > je) break;
     step(P[3], P[2], P[0], P[(PD + 3) & 3], j + 3);
   }
-  if (RES) block_store<NV>(acc, 0u, a.partial + (long long)NV * blockIdx.x);
+  if (RES) block_store<NV>(acc, 0u, part);
+}
+
+// One tile march per block; tiles go to workgroups XCD by XCD.
+template <bool DC, bool RES, bool ACT, bool ADJ, int W>
+__global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int gy, int gz) {
+  __shared__ float lds[2][T2_ROWS][64 * W];
+  __shared__ float4 qlds[2][2 * W][64 * T2_ROWS];
+  const int L = xcd_tile(blockIdx.x, gx * gy * gz);
+  sweep2_tile<DC, RES, ACT, ADJ, W>(a, gx, gy, L, lds, qlds,
+                                    RES ? a.partial + (long long)NV * blockIdx.x : nullptr);
 }
 
 template <bool DC, bool RES, bool ACT>
@@ -909,11 +949,14 @@ __global__ void __launch_bounds__(1024) k_sweep_v4(SweepArgs<float> a, int gx, i
 
 bool vec4_path(const Grid &g) { return (g.nx & 3) == 0; }
 
-// even nx, and 32-bit element offsets for every FP32 array
-bool two_path(const Grid &g) { return (g.nx % T2_W) == 0 && g.n < (1ll << 30); }
+// 32-bit byte offsets for every FP32 array
+bool two_path(const Grid &g) { return g.n < (1ll << 30); }
+
+int two_w(const Grid &g) { return (g.nx & 1) ? 1 : 2; }
 
 dim3 sweep2_grid(const Grid &g, const Tiles &t) {
-  return dim3((unsigned)((g.nx + T2_OUT_X - 1) / T2_OUT_X),
+  const int ox = 62 * two_w(g);
+  return dim3((unsigned)((g.nx + ox - 1) / ox),
               (unsigned)((g.ny + T2_OUT_Y - 1) / T2_OUT_Y),
               (unsigned)((g.nz + t.zc2 - 1) / t.zc2));
 }
@@ -939,18 +982,23 @@ void launch_sweep2(const SweepArgs<float> &a, const Tiles &t, hipStream_t st, bo
   SweepArgs<float> b = a;
   b.zc = t.zc2;
   dim3 block(64, T2_ROWS, 1);
-  if (adj) {
-    // transpose sweeps run only in the correction form
-    with_flags(true, a.partial != nullptr, a.kappa != nullptr, [&](auto, auto res, auto act) {
-      k_sweep2<true, res.value, act.value, true><<<nb, block, 0, st>>>(b, gv.x, gv.y, gv.z);
-    });
-    return;
-  }
-  with_flags(a.r0 != nullptr, a.partial != nullptr, a.kappa != nullptr,
-             [&](auto dc, auto res, auto act) {
-               k_sweep2<dc.value, res.value, act.value, false><<<nb, block, 0, st>>>(b, gv.x,
-                                                                                    gv.y, gv.z);
-             });
+  auto go = [&](auto w) {
+    constexpr int W = decltype(w)::value;
+    if (adj) {
+      // transpose sweeps run only in the correction form
+      with_flags(true, a.partial != nullptr, a.kappa != nullptr, [&](auto, auto res, auto act) {
+        k_sweep2<true, res.value, act.value, true, W><<<nb, block, 0, st>>>(b, gv.x, gv.y, gv.z);
+      });
+      return;
+    }
+    with_flags(a.r0 != nullptr, a.partial != nullptr, a.kappa != nullptr,
+               [&](auto dc, auto res, auto act) {
+                 k_sweep2<dc.value, res.value, act.value, false, W><<<nb, block, 0, st>>>(
+                     b, gv.x, gv.y, gv.z);
+               });
+  };
+  if (two_w(a.g) == 2) go(std::integral_constant<int, 2>{});
+  else go(std::integral_constant<int, 1>{});
 }
 
 dim3 sweep_grid_v4(const Grid &g, const Tiles &t) {
@@ -1082,6 +1130,66 @@ __global__ void __launch_bounds__(1024) k_batch_sweep(const BatchProb *__restric
     }
     if (RES) block_store<NV>(acc, 0u, partial + (long long)NV * t);
   }
+}
+
+// Batched two-sweep launches, correction form, no activity field: persistent blocks (one per
+// CU) take contiguous runs of the work list of (problem, tile) items, XCD by XCD; each item
+// is one tile march of the two-sweep kernel on its problem, whose residual partials go to
+// the item's tile number.
+template <bool RES>
+__global__ void __launch_bounds__(1024) k_batch_sweep2(const BatchProb *__restrict__ probs,
+                                                      const int *__restrict__ tile_prob,
+                                                      const int *__restrict__ work,
+                                                      const int *__restrict__ nwork, int parity,
+                                                      double *__restrict__ partial) {
+  // LDS for two cells per lane; a problem with odd nx (one cell per lane) uses a view of
+  // the same arrays at its smaller shape
+  __shared__ float lds[2][T2_ROWS][128];
+  __shared__ float4 qlds[2][4][64 * T2_ROWS];
+  const int nw = *nwork;
+  const int per = (nw + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int w0 = b * per;
+  const int w1 = min(w0 + per, nw);
+  for (int w = w0; w < w1; ++w) {
+    const int t = work[w];
+    const BatchProb &q = probs[tile_prob[t]];
+    SweepArgs<float> a;
+    a.g = Grid{q.nx, q.ny, q.nz, (long long)q.nx * q.ny * q.nz};
+    a.flags = q.flags;
+    a.w = Faces<float>{q.wx, q.wy, q.wz, q.wxo};
+    a.kappa = nullptr;
+    a.s = parity ? q.s1 : q.s0;
+    a.s_new = parity ? q.s0 : q.s1;
+    a.r0 = q.r0;
+    a.dt = q.dt;
+    a.s_in = 0.f;
+    a.s_eq = 0.f;
+    a.Da = q.Da;
+    a.gscale = 0.f;
+    a.pinned = q.pinned;
+    a.lo = q.lo;
+    a.hi = q.hi;
+    a.partial = nullptr;
+    a.zc = q.zc;
+    double *pp = RES ? partial + (long long)NV * t : nullptr;
+    if (q.nx & 1)
+      sweep2_tile<true, RES, false, false, 1>(
+          a, q.gx, q.gy, t - q.tile0, reinterpret_cast<float (*)[T2_ROWS][64]>(&lds[0][0][0]),
+          reinterpret_cast<float4 (*)[2][64 * T2_ROWS]>(&qlds[0][0][0]), pp);
+    else
+      sweep2_tile<true, RES, false, false, 2>(a, q.gx, q.gy, t - q.tile0, lds, qlds, pp);
+  }
+}
+
+void launch_batch_sweep2(const BatchProb *probs, const int *tile_prob, const int *work,
+                         const int *nwork, int nblocks, int parity, double *partial,
+                         hipStream_t st) {
+  dim3 block(64, T2_ROWS, 1);
+  if (partial)
+    k_batch_sweep2<true><<<nblocks, block, 0, st>>>(probs, tile_prob, work, nwork, parity, partial);
+  else
+    k_batch_sweep2<false><<<nblocks, block, 0, st>>>(probs, tile_prob, work, nwork, parity, partial);
 }
 
 // out[p * NV + k] = sum over problem p's tiles of partial[tile * NV + k], fixed order

@@ -49,12 +49,13 @@ def test_adjoint_matches_oracle(sv, orc, shape, prec):
     assert abs(dlnq - dlnqx) <= tol * abs(dlnqx)
 
 
-@pytest.mark.parametrize("pinned", [False, True])
-def test_adjoint_two_sweep_launches_match_oracle(sv, orc, pinned):
-    """FP32-mode adjoint with one and with two transpose sweeps per launch (shape 128 x 40 x
-    33: several tiles, ragged in y and z), each against the oracle's exact adjoint; held and
-    fibre cells keep psi = 0."""
-    solid, u = case(128, 40, 33, seed=45)
+@pytest.mark.parametrize("shape,pinned", [((128, 40, 33), False), ((128, 40, 33), True),
+                                          ((95, 37, 29), False)])
+def test_adjoint_two_sweep_launches_match_oracle(sv, orc, shape, pinned):
+    """FP32-mode adjoint with one and with two transpose sweeps per launch (several tiles,
+    ragged in y and z; odd nx takes one cell per lane), each against the oracle's exact
+    adjoint; held and fibre cells keep psi = 0."""
+    solid, u = case(*shape, seed=45)
     kappa = None if pinned else I.lognormal_activity(solid, 0.3, seed=8)
     pb = sv.Problem.create(solid, *u, kappa=kappa)
     kw = dict(mode=1, s_in=0.0, s_eq=1.0, Da=0.0) if pinned else {}

@@ -273,9 +273,11 @@ def test_single_cell_and_degenerate(sv):
     assert abs(float(s[0, 0, 0]) - expect) < 1e-13
 
 
-@pytest.mark.parametrize("shape", [(128, 40, 33), (70, 37, 29), (260, 21, 13), (64, 32, 32)])
+@pytest.mark.parametrize("shape", [(128, 40, 33), (70, 37, 29), (260, 21, 13), (64, 32, 32),
+                                   (63, 40, 33), (129, 21, 13)])
 def test_two_sweep_launches_match_single_sweeps(sv, shape):
-    """FP32 sweeps fused two per launch give the same iterates as one sweep per launch."""
+    """FP32 sweeps fused two per launch give the same iterates as one sweep per launch (odd
+    nx: one cell per lane)."""
     nx, ny, nz = shape
     solid, u = fibre_case(nx, ny, nz, 3.0, 0.85, 31, 1.0)
     pb = make(sv, solid, u)
