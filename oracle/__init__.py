@@ -370,3 +370,44 @@ def exact_adjoint(pb: Problem, method="auto", tol=1e-14):
     else:
         x = _krylov(AT, g, tol)
     return x.reshape(pb.solid.shape)
+
+
+# ------------------------------------------------------------------------------------
+# Iterative upsampling (Sec. "Incompressible Fluid Flow", its part on iterative upsampling:
+# converge on the unrefined grid, then start the refined problem from the interpolated
+# steady state).  Applied to the SOC solve with a grid coarsened by two in every direction.
+# ------------------------------------------------------------------------------------
+
+def _pair_sum_half(a, b, c, d):
+    """((a + b) + (c + d)) / 2: the four fine faces under a coarse face, in a fixed order."""
+    return ((a + b) + (c + d)) * 0.5
+
+
+def coarsen(pb: Problem) -> Problem:
+    """The problem on the grid coarsened by two in every direction (even nx, ny, nz).
+
+    A coarse cell is fibre iff all eight children are fibre (so every face of a coarse fibre
+    cell lies on fine fibre faces and carries no flux, and every coarse pore cell holds a
+    fine pore cell connected to the inlet).  A coarse face velocity, in coarse grid units
+    (h doubled, D unchanged), is half the sum of its four fine face velocities: the same
+    physical flux.  Reaction per coarse fibre face 2 Da (Da = k h / D with h doubled).  The
+    activity field is not carried (the coarse solve is only a starting state)."""
+    nz, ny, nx = pb.solid.shape
+    assert nx % 2 == 0 and ny % 2 == 0 and nz % 2 == 0, "coarsening needs even dimensions"
+    sol = pb.solid.astype(bool).reshape(nz // 2, 2, ny // 2, 2, nx // 2, 2)
+    csolid = sol.all(axis=(1, 3, 5)).astype(np.uint8)
+    fx = pb.ux[:, :, 0::2]                       # x faces at even fine x: (nz, ny, nx/2 + 1)
+    ux = _pair_sum_half(fx[0::2, 0::2], fx[0::2, 1::2], fx[1::2, 0::2], fx[1::2, 1::2])
+    fy = pb.uy[:, 0::2, :]                       # (nz, ny/2 + 1, nx)
+    uy = _pair_sum_half(fy[0::2, :, 0::2], fy[0::2, :, 1::2], fy[1::2, :, 0::2], fy[1::2, :, 1::2])
+    fz = pb.uz[0::2]                             # (nz/2 + 1, ny, nx)
+    uz = _pair_sum_half(fz[:, 0::2, 0::2], fz[:, 0::2, 1::2], fz[:, 1::2, 0::2], fz[:, 1::2, 1::2])
+    return Problem(csolid, ux, uy, uz, s_in=pb.s_in, s_eq=pb.s_eq, Da=2.0 * pb.Da,
+                   pinned=pb.pinned)
+
+
+def prolongate(pb: Problem, s_coarse):
+    """Fine starting state from a coarse one: each fine pore cell takes its parent's value
+    (piecewise-constant interpolation), fibre cells 0."""
+    s = np.repeat(np.repeat(np.repeat(_c(s_coarse, np.float64), 2, axis=0), 2, axis=1), 2, axis=2)
+    return np.where(pb.solid == 0, s, 0.0)

@@ -203,6 +203,8 @@ def darcy_velocity(solid, peclet, rtol=1e-12, device=None, max_iter=400000,
     gout_np = np.zeros((B, nz, ny, nx), dtype=np.float64)   # outlet conductance per cell
     for b, m in enumerate(masks):
         mz, my, mx = m.shape
+        if not (m[:, :, 0] == 0).any() or not (m[:, :, mx - 1] == 0).any():
+            raise ValueError(f"geometry {b}: no pore cell in the inlet or outlet plane (no flow)")
         pore_np[b, :mz, :my, :mx] = (m == 0)
         gin_np[b, :mz, :my] = 2.0 * (m[:, :, 0] == 0)
         gout_np[b, :mz, :my, mx - 1] = 2.0 * (m[:, :, mx - 1] == 0)
