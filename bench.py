@@ -176,6 +176,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-upsampling", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--tiles", default=None, help="tile_y,z_chunk for the sweeps")
@@ -308,6 +309,27 @@ def main():
                              "forward_sweeps": stf.iterations, "dU_dlnq": dlnq,
                              "status": sta.status}
         log(f"adjoint Pe={pe}: {ta:.2f}s vs forward {stf.seconds:.2f}s")
+    if not args.no_upsampling and nx % 2 == 0 and ny % 2 == 0 and nz % 2 == 0:
+        # iterative upsampling: coarse (2x) steady state as the fine solve's start, against
+        # the plain solve from s = s_in, at one flow rate
+        pe = 1.0 if 1.0 in pes else pes[0]
+        pb.set_flow_rate(pe)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, stp = sv.solve_soc_steady(pb.ctx, p, want_state=False)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t
+        t = time.perf_counter()
+        _, stu, stc = sv.solve_soc_upsampled(pb.ctx, p, want_state=False)
+        torch.cuda.synchronize()
+        tu = time.perf_counter() - t
+        result["upsampling"] = {"peclet": pe, "plain_seconds": tp, "upsampled_seconds": tu,
+                                "speedup": tp / tu, "plain_sweeps": stp.iterations,
+                                "fine_sweeps": stu.iterations, "coarse_sweeps": stc.iterations,
+                                "coarse_seconds": stc.seconds, "U_plain": stp.U,
+                                "U_upsampled": stu.U, "status": stu.status}
+        log(f"upsampling Pe={pe}: {tu:.2f}s ({stc.iterations} coarse + {stu.iterations} fine "
+            f"sweeps) vs plain {tp:.2f}s ({stp.iterations} sweeps)")
     if not args.no_accuracy:
         t = time.time()
         result["accuracy"] = accuracy_legs(sv)

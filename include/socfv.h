@@ -201,6 +201,33 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
                       double *const *s_out, socfv_stats *st, void *hip_stream);
 
 /*
+ * Iterative upsampling: converge on the unrefined grid, then start the refined problem from
+ * the interpolated steady state (the paper's technique for the flow, Sec. "Incompressible
+ * Fluid Flow"), here for this solve with the grid coarsened by two in every direction.
+ *
+ * socfv_coarsen writes the coarse problem of the context's current geometry and velocity
+ * (q included); nx, ny, nz must be even (INVALID_ARG otherwise; velocity must be set).
+ *   solid_c: device, uint8 (nz/2, ny/2, nx/2): 1 where all eight children are fibre.
+ *   ux_c, uy_c, uz_c: device, FP64, the staggered layout above for the coarse grid: each
+ *   coarse face velocity in coarse grid units (h doubled, same physical flux) is
+ *   ((v00 + v01) + (v10 + v11)) / 2 over its four fine faces, v_ab with a the offset along
+ *   the slower transverse axis (z for x and y faces, y for z faces) and b along the faster.
+ * Buffers are the caller's; the call returns when they are written.
+ *
+ * socfv_solve_soc_upsampled solves the coarse problem (reaction 2 Da per coarse fibre face,
+ * uniform activity, the other parameters of p) to steady state, prolongates it (each fine
+ * pore cell takes its parent's value) and solves the fine problem from that state, which
+ * has the plain solve's fixed point.  st: the fine solve's statistics with seconds covering
+ * the whole call; coarse_st (nullable): the coarse solve's.  s_out as in
+ * socfv_solve_soc_steady.  Temporary device memory is allocated and freed inside the call.
+ * Returns the fine solve's status (or the first error).
+ */
+int socfv_coarsen(socfv_ctx *c, uint8_t *solid_c, double *ux_c, double *uy_c, double *uz_c,
+                  void *hip_stream);
+int socfv_solve_soc_upsampled(socfv_ctx *c, const socfv_params *p, double *s_out,
+                              socfv_stats *st, socfv_stats *coarse_st, void *hip_stream);
+
+/*
  * Launch shapes.  Single sweeps work on (64 x tile_y) lanes marching z_chunk cells along z;
  * with two_sweeps set (the default), FP32 sweeps on grids with even nx run two sweeps per
  * launch on 64 x 16 lanes marching z_chunk2 cells.  socfv_set_tiles overrides them for a

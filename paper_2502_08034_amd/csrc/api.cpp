@@ -864,6 +864,61 @@ int socfv_solve_soc_adjoint(socfv_ctx *c, const socfv_params *p, double *dU_dkap
   return status;
 }
 
+int socfv_coarsen(socfv_ctx *c, uint8_t *solid_c, double *ux_c, double *uy_c, double *uz_c,
+                  void *hip_stream) {
+  if (!c) return fail(SOCFV_INVALID_ARG, "NULL context");
+  if (!solid_c || !ux_c || !uy_c || !uz_c) return fail(SOCFV_INVALID_ARG, "NULL output buffer");
+  if (!c->have_velocity) return fail(SOCFV_INVALID_ARG, "velocity not set");
+  const Grid &g = c->g;
+  if ((g.nx | g.ny | g.nz) & 1)
+    return fail(SOCFV_INVALID_ARG, "coarsening needs even dimensions (%d %d %d)", g.nx, g.ny, g.nz);
+  TRY(enter(c, hip_stream));
+  launch_coarse_mask(g, c->flags, solid_c, c->st);
+  launch_restrict(g, faces64(c), ux_c, uy_c, uz_c, c->st);
+  HIPCHK(hipGetLastError());
+  return leave(c, hip_stream);
+}
+
+int socfv_solve_soc_upsampled(socfv_ctx *c, const socfv_params *p, double *s_out,
+                              socfv_stats *st, socfv_stats *coarse_st, void *hip_stream) {
+  const double t0 = now_s();
+  if (!c) return fail(SOCFV_INVALID_ARG, "NULL context");
+  TRY(check_params(p));
+  const Grid g = c->g;
+  const int nxc = g.nx / 2, nyc = g.ny / 2, nzc = g.nz / 2;
+  const size_t nc = (size_t)nxc * nyc * nzc;
+  uint8_t *solid = nullptr;
+  double *ux = nullptr, *uy = nullptr, *uz = nullptr, *sc = nullptr, *sf = nullptr;
+  socfv_ctx *cc = nullptr;
+  const int rc = [&]() -> int {
+    HIPCHK(hipMalloc(&solid, nc));
+    HIPCHK(hipMalloc(&ux, sizeof(double) * (size_t)nzc * nyc * (nxc + 1)));
+    HIPCHK(hipMalloc(&uy, sizeof(double) * (size_t)nzc * (nyc + 1) * nxc));
+    HIPCHK(hipMalloc(&uz, sizeof(double) * (size_t)(nzc + 1) * nyc * nxc));
+    HIPCHK(hipMalloc(&sc, sizeof(double) * nc));
+    HIPCHK(hipMalloc(&sf, sizeof(double) * (size_t)g.n));
+    TRY(socfv_coarsen(c, solid, ux, uy, uz, hip_stream));
+    TRY(socfv_setup_geometry(&cc, nxc, nyc, nzc, solid, hip_stream));
+    TRY(socfv_set_velocity(cc, ux, uy, uz, 1.0, hip_stream));
+    socfv_params pc = *p;
+    pc.Da = 2.0 * p->Da;
+    socfv_stats cs{};
+    // a coarse solve that stops at max_iter still gives a starting state
+    TRY(socfv_solve_soc_steady(cc, &pc, nullptr, sc, &cs, hip_stream));
+    if (coarse_st) *coarse_st = cs;
+    TRY(enter(c, hip_stream));
+    launch_prolong(g, c->flags, sc, sf, c->st);
+    HIPCHK(hipGetLastError());
+    TRY(leave(c, hip_stream));
+    const int r = socfv_solve_soc_steady(c, p, sf, s_out, st, hip_stream);
+    if (st) st->seconds = now_s() - t0;
+    return r;
+  }();
+  if (cc) socfv_destroy(cc);
+  hfree(solid); hfree(ux); hfree(uy); hfree(uz); hfree(sc); hfree(sf);
+  return rc;
+}
+
 int socfv_set_tiles(socfv_ctx *c, int tile_y, int z_chunk, int z_chunk2, int two_sweeps) {
   if (!c) return fail(SOCFV_INVALID_ARG, "NULL context");
   if (tile_y != 0) {

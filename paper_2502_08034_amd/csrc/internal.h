@@ -122,6 +122,15 @@ void launch_batch_sweep2(const BatchProb *probs, const int *tile_prob, const int
 void launch_batch_reduce(const BatchProb *probs, int n, const double *partial, double *out,
                          hipStream_t st);
 
+// Iterative upsampling (even nx, ny, nz): coarse mask (fibre iff all eight children are
+// fibre), coarse staggered FP64 face velocities (half the sum of the four fine faces), and
+// the prolongation of a coarse state to the fine pore cells.
+void launch_coarse_mask(const Grid &g, const uint8_t *flags, uint8_t *solid_c, hipStream_t st);
+void launch_restrict(const Grid &g, const Faces<double> &w, double *ux_c, double *uy_c,
+                     double *uz_c, hipStream_t st);
+void launch_prolong(const Grid &g, const uint8_t *flags, const double *s_c, double *s_f,
+                    hipStream_t st);
+
 // Launch shapes.
 struct Tiles {
   int ty;   // threads (rows) along y per block; x is one 64-wide wave

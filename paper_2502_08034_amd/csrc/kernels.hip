@@ -1609,6 +1609,108 @@ void launch_fill_f64(double *p, long long n, double v, hipStream_t st) {
   k_fill<double><<<fill_blocks(n), 256, 0, st>>>(p, n, v);
 }
 
+// ------------------------------------------------------------------------------------
+// Iterative upsampling: the problem coarsened by two in every direction, and the
+// prolongation of its steady state (converge on the unrefined grid, then start the refined
+// problem from the interpolated state; Sec. "Incompressible Fluid Flow")
+// ------------------------------------------------------------------------------------
+
+// coarse cell fibre iff all eight children are fibre
+__global__ void __launch_bounds__(256) k_coarse_mask(Grid g, const uint8_t *__restrict__ flags,
+                                                     uint8_t *__restrict__ solid_c) {
+  const int nxc = g.nx / 2, nyc = g.ny / 2;
+  const long long nc = (long long)nxc * nyc * (g.nz / 2);
+  for (long long c = blockIdx.x * 256ll + threadIdx.x; c < nc; c += 256ll * gridDim.x) {
+    const int ic = (int)(c % nxc), jc = (int)((c / nxc) % nyc), kc = (int)(c / ((long long)nxc * nyc));
+    bool all = true;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int d = 0; d < 2; ++d) {
+          const long long i = (2 * ic + d) + (long long)g.nx * ((2 * jc + b) + (long long)g.ny * (2 * kc + a));
+          all = all && !(flags[i] & FL_PORE);
+        }
+    solid_c[c] = all ? 1 : 0;
+  }
+}
+
+// Coarse staggered face velocities in coarse grid units (h doubled, same physical flux):
+// ((v00 + v01) + (v10 + v11)) / 2 over the four fine faces of a coarse face, v_ab with a the
+// offset along the slower transverse axis (z for x and y faces, y for z faces) and b along
+// the faster one.  Fine faces come from the per-cell lower faces and the outlet faces; the
+// top y and z walls carry 0.  One thread per coarse face over ux, then uy, then uz.
+__global__ void __launch_bounds__(256) k_restrict(Grid g, Faces<double> w, double *__restrict__ ux_c,
+                                                  double *__restrict__ uy_c,
+                                                  double *__restrict__ uz_c) {
+  const int nx = g.nx, ny = g.ny;
+  const int nxc = g.nx / 2, nyc = g.ny / 2, nzc = g.nz / 2;
+  const long long nux = (long long)nzc * nyc * (nxc + 1);
+  const long long nuy = (long long)nzc * (nyc + 1) * nxc;
+  const long long nuz = (long long)(nzc + 1) * nyc * nxc;
+  auto at = [&](int x, int y, int z) { return x + (long long)nx * (y + (long long)ny * z); };
+  for (long long t = blockIdx.x * 256ll + threadIdx.x; t < nux + nuy + nuz; t += 256ll * gridDim.x) {
+    double v[2][2];
+    if (t < nux) {
+      const int ic = (int)(t % (nxc + 1)), jc = (int)((t / (nxc + 1)) % nyc);
+      const int kc = (int)(t / ((long long)(nxc + 1) * nyc));
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+          const int y = 2 * jc + b, z = 2 * kc + a;
+          v[a][b] = ic < nxc ? w.wx[at(2 * ic, y, z)] : w.wxo[y + (long long)ny * z];
+        }
+      ux_c[t] = ((v[0][0] + v[0][1]) + (v[1][0] + v[1][1])) * 0.5;
+    } else if (t < nux + nuy) {
+      const long long u = t - nux;
+      const int ic = (int)(u % nxc), jc = (int)((u / nxc) % (nyc + 1));
+      const int kc = (int)(u / ((long long)nxc * (nyc + 1)));
+      if (jc == nyc) {
+        uy_c[u] = 0.0;
+        continue;
+      }
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) v[a][b] = w.wy[at(2 * ic + b, 2 * jc, 2 * kc + a)];
+      uy_c[u] = ((v[0][0] + v[0][1]) + (v[1][0] + v[1][1])) * 0.5;
+    } else {
+      const long long u = t - nux - nuy;
+      const int ic = (int)(u % nxc), jc = (int)((u / nxc) % nyc);
+      const int kc = (int)(u / ((long long)nxc * nyc));
+      if (kc == nzc) {
+        uz_c[u] = 0.0;
+        continue;
+      }
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) v[a][b] = w.wz[at(2 * ic + b, 2 * jc + a, 2 * kc)];
+      uz_c[u] = ((v[0][0] + v[0][1]) + (v[1][0] + v[1][1])) * 0.5;
+    }
+  }
+}
+
+// fine starting state: each pore cell takes its parent's coarse value, fibre cells 0
+__global__ void __launch_bounds__(256) k_prolong(Grid g, const uint8_t *__restrict__ flags,
+                                                 const double *__restrict__ s_c,
+                                                 double *__restrict__ s_f) {
+  const int nxc = g.nx / 2, nyc = g.ny / 2;
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < g.n; i += 256ll * gridDim.x) {
+    const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny);
+    const int z = (int)(i / ((long long)g.nx * g.ny));
+    const long long c = (x / 2) + (long long)nxc * ((y / 2) + (long long)nyc * (z / 2));
+    s_f[i] = (flags[i] & FL_PORE) ? s_c[c] : 0.0;
+  }
+}
+
+void launch_coarse_mask(const Grid &g, const uint8_t *flags, uint8_t *solid_c, hipStream_t st) {
+  k_coarse_mask<<<fill_blocks(g.n / 8 + 1), 256, 0, st>>>(g, flags, solid_c);
+}
+
+void launch_restrict(const Grid &g, const Faces<double> &w, double *ux_c, double *uy_c,
+                     double *uz_c, hipStream_t st) {
+  k_restrict<<<fill_blocks(g.n / 8 * 3 + 1), 256, 0, st>>>(g, w, ux_c, uy_c, uz_c);
+}
+
+void launch_prolong(const Grid &g, const uint8_t *flags, const double *s_c, double *s_f,
+                    hipStream_t st) {
+  k_prolong<<<fill_blocks(g.n), 256, 0, st>>>(g, flags, s_c, s_f);
+}
+
 __global__ void __launch_bounds__(256) k_init_state(Grid g, const uint8_t *__restrict__ flags,
                                                     const double *__restrict__ s_init,
                                                     double s_in, double s_eq, int pinned,

@@ -68,6 +68,9 @@ def _load():
         "socfv_solve_soc_adjoint": (i, [P, C.POINTER(Params), P, C.POINTER(d), P,
                                         C.POINTER(Stats), P]),
         "socfv_batch_solve": (i, [i, PP, C.POINTER(Params), PP, C.POINTER(Stats), P]),
+        "socfv_coarsen": (i, [P, P, P, P, P, P]),
+        "socfv_solve_soc_upsampled": (i, [P, C.POINTER(Params), P, C.POINTER(Stats),
+                                          C.POINTER(Stats), P]),
         "socfv_set_tiles": (i, [P, i, i, i, i]),
         "socfv_autotune": (i, [P, i, C.POINTER(C.c_int), P]),
         "socfv_info": (i, [P, C.POINTER(C.c_int), C.POINTER(C.c_long)]),
@@ -234,6 +237,31 @@ def batch_solve(ctxs, ps, want_states=True):
     code = _lib.socfv_batch_solve(n, hs, pa, outs, sts, _stream())
     _check(code)
     return states, list(sts)
+
+
+def coarsen(ctx: Context):
+    """The problem coarsened by two in every direction: (solid_c uint8, ux_c, uy_c, uz_c
+    float64), CUDA tensors in the staggered layout of the coarse grid."""
+    nz, ny, nx = ctx.shape
+    nzc, nyc, nxc = nz // 2, ny // 2, nx // 2
+    dev = "cuda"
+    solid = torch.empty((nzc, nyc, nxc), dtype=torch.uint8, device=dev)
+    ux = torch.empty((nzc, nyc, nxc + 1), dtype=torch.float64, device=dev)
+    uy = torch.empty((nzc, nyc + 1, nxc), dtype=torch.float64, device=dev)
+    uz = torch.empty((nzc + 1, nyc, nxc), dtype=torch.float64, device=dev)
+    _check(_lib.socfv_coarsen(ctx.handle, _ptr(solid, torch.uint8), _ptr(ux, torch.float64),
+                              _ptr(uy, torch.float64), _ptr(uz, torch.float64), _stream()))
+    return solid, ux, uy, uz
+
+
+def solve_soc_upsampled(ctx: Context, p: Params, want_state=True):
+    """Iterative upsampling: coarse steady state, prolongated, as the fine solve's start.
+    Returns (s, stats of the fine solve, stats of the coarse solve)."""
+    s = torch.empty(ctx.shape, dtype=torch.float64, device="cuda") if want_state else None
+    st, cst = Stats(), Stats()
+    _check(_lib.socfv_solve_soc_upsampled(ctx.handle, C.byref(p), _ptr(s, torch.float64),
+                                          C.byref(st), C.byref(cst), _stream()))
+    return s, st, cst
 
 
 def set_tiles(ctx: Context, tile_y=0, z_chunk=0, z_chunk2=0, two_sweeps=-1):
