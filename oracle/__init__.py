@@ -81,6 +81,8 @@ def lib():
         L.orc_export_rows.restype = None
         L.orc_apply_AT.argtypes = [i, i, i, P, P, P, P, P, P, i, P, P, i]
         L.orc_apply_AT.restype = None
+        L.orc_nernst.argtypes = [i, i, i, P, P, P, P, P, P, d, d, d, d, d, l, i, P, P, P]
+        L.orc_nernst.restype = i
         L.orc_num_threads.argtypes = []; L.orc_num_threads.restype = i
         _lib = L
     return _lib
@@ -411,3 +413,25 @@ def prolongate(pb: Problem, s_coarse):
     (piecewise-constant interpolation), fibre cells 0."""
     s = np.repeat(np.repeat(np.repeat(_c(s_coarse, np.float64), 2, axis=0), 2, axis=1), 2, axis=2)
     return np.where(pb.solid == 0, s, 0.0)
+
+
+# ------------------------------------------------------------------------------------
+# Explicit Nernst model (Sec. "Steady State Reaction Model (Nernst)", Algorithm "Explicit
+# Nernst Model"; electrode value sigma(V - eta) of Eq. (nernst-model-s-update))
+# ------------------------------------------------------------------------------------
+
+def nernst(pb: Problem, omega=0.5, cfl=0.4, tol=1e-10, max_iter=10**7, check_every=1,
+           s0=None, eta0=None):
+    """Electrode cells (reactive pore cells) held at sigma(V - eta), eta relaxed toward the
+    overpotential that balances the transport step (steps in the order of ``orc_nernst``).  Finite-rate problems with 0 < s_eq < 1 and Da > 0.  Returns
+    (s, eta, info)."""
+    assert not pb.pinned and 0.0 < pb.s_eq < 1.0 and pb.Da > 0.0
+    s = pb.initial_state() if s0 is None else np.array(s0, dtype=np.float64)
+    eta = np.zeros(pb.solid.shape) if eta0 is None else np.array(eta0, dtype=np.float64)
+    s = _c(s, np.float64)
+    eta = _c(eta, np.float64)
+    out = np.zeros(4)
+    st = lib().orc_nernst(*pb._args(), pb.s_in, pb.s_eq, float(omega), float(cfl), float(tol),
+                          int(max_iter), int(check_every), _p(s), _p(eta), _p(out))
+    return s, eta, {"status": int(st), "iterations": int(out[0]), "residual": float(out[1]),
+                    "dt": float(out[2]), "tau": float(out[3])}

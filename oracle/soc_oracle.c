@@ -327,6 +327,76 @@ int orc_solve(int nx, int ny, int nz, const uint8_t *solid, const double *ux,
 }
 
 /*
+ * Explicit Nernst model (Sec. "Steady State Reaction Model (Nernst)", Algorithm "Explicit
+ * Nernst Model", with the electrode value of Eq. (nernst-model-s-update)).  Electrode cells
+ * are the reactive pore cells (n_f > 0).  One iteration:
+ *   1. transport step on every pore cell, s' = s + dt R_t(s), R_t the residual without the
+ *      reaction term (advection and diffusion: the same faces and boundary values);
+ *   2. on electrode cells, the instantaneous overpotential of Eq. (nernst-eta-inst-def) with
+ *      D lap s replaced by the transport rate (s' - s) / dt = R_t:
+ *        eta_I = 2 asinh(-R_t / (2 c sqrt(s (1 - s)))),  c = a k0 per cell = lam / K,
+ *      K = e^{V/2} + e^{-V/2} = 1 / sqrt(s_eq (1 - s_eq)) the affine rate's slope at
+ *      alpha = 1/2 (lam = Da kappa n_f carries a k0 K);
+ *   3. eta <- (1 - omega) eta + omega eta_I (Eq. (nernst-model-eta-update));
+ *   4. s' = sigma(V - eta) on electrode cells (Eq. (nernst-model-s-update)), V = logit(s_eq).
+ * Stop when tau rms((s' - s) / dt) < tol, checked every check_every iterations; dt from the
+ * transport-only diagonal.  The caller passes the start (s on pore cells, eta on electrode
+ * cells); electrode cells start at sigma(V - eta).  0 < s_eq < 1, lam > 0 on electrode cells.
+ * out: [iterations, residual, dt, tau].  Returns 0 on convergence, 1 otherwise.
+ */
+int orc_nernst(int nx, int ny, int nz, const uint8_t *solid, const double *ux,
+               const double *uy, const double *uz, const double *lam, const int8_t *nf,
+               double s_in, double s_eq, double omega, double cfl, double tol, long max_iter,
+               int check_every, double *s, double *eta, double *out) {
+    long n = (long)nx * ny * nz;
+    double *lam0 = (double *)calloc((size_t)n, sizeof(double));
+    double *R = (double *)malloc(sizeof(double) * (size_t)n);
+    double dt = cfl / orc_max_diag(nx, ny, nz, solid, ux, uy, uz, lam0, nf, 0);
+    double tau = (double)n / orc_inflow(nx, ny, nz, solid, ux);
+    double npore = (double)count_pore(n, solid);
+    double V = log(s_eq / (1.0 - s_eq));
+    double K = 1.0 / sqrt(s_eq * (1.0 - s_eq));
+    for (long P = 0; P < n; ++P) {
+        if (solid[P]) { s[P] = 0.0; eta[P] = 0.0; }
+        else if (nf[P] > 0) s[P] = 1.0 / (1.0 + exp(eta[P] - V));
+        else eta[P] = 0.0;
+    }
+    long it = 0;
+    double res = INFINITY;
+    int status = 1;
+    if (check_every < 1) check_every = 1;
+    while (it < max_iter) {
+        orc_residual(nx, ny, nz, solid, ux, uy, uz, lam0, nf, s_in, s_eq, 0, s, R);
+        double ss = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : ss)
+        for (long P = 0; P < n; ++P) {
+            if (solid[P]) continue;
+            double sn = s[P] + dt * R[P];
+            if (nf[P] > 0) {
+                double c = lam[P] / K;
+                double sp = s[P];
+                double eta_i = 2.0 * asinh(-R[P] / (2.0 * c * sqrt(sp * (1.0 - sp))));
+                eta[P] = (1.0 - omega) * eta[P] + omega * eta_i;
+                sn = 1.0 / (1.0 + exp(eta[P] - V));
+            }
+            double d = (sn - s[P]) / dt;
+            ss += d * d;
+            s[P] = sn;
+        }
+        ++it;
+        if (it % check_every == 0) {
+            res = tau * sqrt(ss / npore);
+            if (!(res == res)) break;
+            if (res < tol) { status = 0; break; }
+        }
+    }
+    free(lam0);
+    free(R);
+    out[0] = (double)it; out[1] = res; out[2] = dt; out[3] = tau;
+    return status;
+}
+
+/*
  * Fixed number of iterations (no residual checks): the timing leg uses this.
  */
 void orc_iterate(int nx, int ny, int nz, const uint8_t *solid, const double *ux,
