@@ -201,6 +201,27 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
                       double *const *s_out, socfv_stats *st, void *hip_stream);
 
 /*
+ * Explicit Nernst model (Sec. "Steady State Reaction Model (Nernst)", Algorithm "Explicit
+ * Nernst Model", with the electrode value of Eq. (nernst-model-s-update)); FP64.  Electrode
+ * cells (pore cells with a fibre face) are held at sigma(V - eta), V = logit(s_eq); every
+ * iteration takes the transport step (advection and diffusion) on all pore cells, then on
+ * electrode cells eta <- (1 - omega) eta + omega eta_I with eta_I = 2 asinh(-R_t /
+ * (2 a k0 sqrt(s (1 - s)))) (Eq. (nernst-eta-inst-def), R_t the transport rate of the step,
+ * a k0 = Da kappa n_f sqrt(s_eq (1 - s_eq)) per cell) and s = sigma(V - eta).  Its fixed
+ * point is the finite-rate steady state of socfv_solve_soc_steady (alpha = 1/2).
+ * Needs FINITE_RATE, 0 < s_eq < 1, Da > 0, 0 < omega <= 1 (INVALID_ARG otherwise).  The
+ * relaxation is stable for omega below about 2 / (1 + M), M = D_P sqrt(s (1 - s)) / (a k0
+ * cosh(eta / 2)) with D_P the transport diagonal (~6 + advection): small omega for slow
+ * kinetics; DIVERGED reports an unstable omega.  Uses p's s_in, s_eq, Da, cfl (on the
+ * transport-only diagonal), tol (on tau rms((s' - s) / dt)), max_iter, check_every.
+ * Outputs: s_out, eta_out (device, FP64 (nz, ny, nx), nullable), st (iterations, residual,
+ * U and the balance).  The state becomes the context's forward state (as after a solve with
+ * p).
+ */
+int socfv_solve_nernst(socfv_ctx *c, const socfv_params *p, double omega, double *s_out,
+                       double *eta_out, socfv_stats *st, void *hip_stream);
+
+/*
  * Iterative upsampling: converge on the unrefined grid, then start the refined problem from
  * the interpolated steady state (the paper's technique for the flow, Sec. "Incompressible
  * Fluid Flow"), here for this solve with the grid coarsened by two in every direction.

@@ -864,6 +864,83 @@ int socfv_solve_soc_adjoint(socfv_ctx *c, const socfv_params *p, double *dU_dkap
   return status;
 }
 
+int socfv_solve_nernst(socfv_ctx *c, const socfv_params *p, double omega, double *s_out,
+                       double *eta_out, socfv_stats *st, void *hip_stream) {
+  const double t0 = now_s();
+  if (!c) return fail(SOCFV_INVALID_ARG, "NULL context");
+  TRY(check_params(p));
+  if (!c->have_velocity) return fail(SOCFV_INVALID_ARG, "velocity not set");
+  if (p->mode != SOCFV_FINITE_RATE)
+    return fail(SOCFV_INVALID_ARG, "the Nernst model is for finite-rate kinetics");
+  if (!(p->s_eq > 0.0 && p->s_eq < 1.0) || !(p->Da > 0.0))
+    return fail(SOCFV_INVALID_ARG, "the Nernst model needs 0 < s_eq < 1 and Da > 0");
+  if (!(omega > 0.0 && omega <= 1.0)) return fail(SOCFV_INVALID_ARG, "omega must be in (0, 1]");
+  const long long n = c->g.n;
+  double *eta = nullptr;
+  const int rc = [&]() -> int {
+    TRY(enter(c, hip_stream));
+    // time step from the transport-only diagonal (the reaction is on the electrode's value)
+    socfv_params pt = *p;
+    pt.Da = 0.0;
+    Solver S{c, &pt};
+    TRY(S.setup());
+    HIPCHK(hipMalloc(&eta, sizeof(double) * (size_t)n));
+    launch_fill_f64(eta, n, 0.0, c->st);
+    // s_in on pore cells, s_eq = sigma(V - 0) on electrode cells
+    launch_init_state(c->g, c->flags, nullptr, p->s_in, p->s_eq, 1, c->s64[0], c->st);
+    HIPCHK(hipGetLastError());
+    NernstArgs a;
+    a.g = c->g; a.flags = c->flags; a.w = faces64(c); a.kappa = c->kappa; a.eta = eta;
+    a.s_in = p->s_in; a.dt = S.dt; a.Da = p->Da; a.omega = omega;
+    a.V = std::log(p->s_eq / (1.0 - p->s_eq));
+    a.K = 1.0 / std::sqrt(p->s_eq * (1.0 - p->s_eq));
+    a.zc = S.t.zc;
+    const int K = S.chunk_len();
+    int cur = 0, status = SOCFV_NOT_CONVERGED;
+    double res = INFINITY, out[NV];
+    while (S.it < p->max_iter) {
+      const long k = std::min<long>(K, p->max_iter - S.it);
+      for (long j = 0; j < k; ++j) {
+        a.s = c->s64[cur];
+        a.s_new = c->s64[cur ^ 1];
+        a.partial = j == k - 1 ? c->partial : nullptr;
+        launch_nernst(a, S.t, c->st);
+        cur ^= 1;
+      }
+      HIPCHK(hipGetLastError());
+      TRY(reduce_to_host(c, (int)S.nblk, NV, 0u, out));
+      S.it += k;
+      S.it64 += k;
+      res = S.res_of(out[0]);
+      if (!std::isfinite(res) || out[1] > 0)
+        return fail(SOCFV_DIVERGED, "Nernst iteration diverged at %ld (residual %g; omega %g may "
+                    "be too large for these kinetics)", S.it, res, omega);
+      if (res < p->tol) { status = SOCFV_OK; break; }
+    }
+    // the Nernst steady state is the finite-rate model's: keep it as the context's state
+    c->have_state = true;
+    c->state_buf = cur;
+    c->last_p = *p;
+    socfv_stats s{};
+    TRY(eval_outputs(c, p, c->s64[cur], &s));
+    if (s_out)
+      HIPCHK(hipMemcpyAsync(s_out, c->s64[cur], sizeof(double) * (size_t)n,
+                            hipMemcpyDeviceToDevice, c->st));
+    if (eta_out)
+      HIPCHK(hipMemcpyAsync(eta_out, eta, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice,
+                            c->st));
+    TRY(leave(c, hip_stream));
+    s.iterations = S.it; s.it_fp64 = S.it64; s.status = status; s.residual = res;
+    s.dt = S.dt; s.tau = S.tau; s.sweeps_fp64 = S.it64;
+    s.seconds = now_s() - t0;
+    if (st) *st = s;
+    if (status == SOCFV_NOT_CONVERGED) fail(status, "Nernst iteration not converged (%g)", res);
+    return status;
+  }();
+  hfree(eta);
+  return rc;
+}
+
 int socfv_coarsen(socfv_ctx *c, uint8_t *solid_c, double *ux_c, double *uy_c, double *uz_c,
                   void *hip_stream) {
   if (!c) return fail(SOCFV_INVALID_ARG, "NULL context");

@@ -136,8 +136,26 @@ struct Tiles {
   int ty;   // threads (rows) along y per block; x is one 64-wide wave
   int zc;   // z cells marched per block
   int zc2;  // z cells per block of the two-sweep kernel
-  int two;  // FP32 sweeps two per launch where the four-cell path applies
+  int two;  // FP32 sweeps two per launch (shapes below 2^30 cells)
 };
+
+// Explicit Nernst model (FP64): transport step on every pore cell; electrode (reactive)
+// cells take sigma(V - eta) with eta relaxed toward the overpotential balancing the
+// transport step.  eta is updated in place (each cell touches only its own).
+struct NernstArgs {
+  Grid g;
+  const uint8_t *flags;
+  Faces<double> w;
+  const float *kappa;   // nullable: uniform activity 1
+  const double *s;
+  double *s_new;
+  double *eta;
+  double s_in, dt, Da, omega, V, K;   // V = logit(s_eq), K = 1 / sqrt(s_eq (1 - s_eq))
+  double *partial;      // nullable: per-block [sum ((s'-s)/dt)^2, non-finite, -, -]
+  int zc;
+};
+void launch_nernst(const NernstArgs &a, const Tiles &t, hipStream_t st);
+
 
 dim3 sweep_grid(const Grid &g, const Tiles &t);
 // FP32 sweeps use four cells per lane when nx % 4 == 0 (grid: 256 x cells per block)

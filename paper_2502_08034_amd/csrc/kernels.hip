@@ -1610,6 +1610,77 @@ void launch_fill_f64(double *p, long long n, double v, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------------------------
+// Explicit Nernst model (Sec. "Steady State Reaction Model (Nernst)", Algorithm "Explicit
+// Nernst Model"; electrode value of Eq. (nernst-model-s-update)), FP64
+// ------------------------------------------------------------------------------------
+
+// One iteration: s' = s + dt R_t(s) on pore cells (R_t: advection and diffusion, the
+// reaction term left out); on electrode cells eta_I = 2 asinh(-R_t / (2 c sqrt(s (1 - s))))
+// (Eq. (nernst-eta-inst-def) with D lap s replaced by the transport rate), c = a k0 =
+// Da kappa n_f / K, eta <- (1 - omega) eta + omega eta_I (Eq. (nernst-model-eta-update)) and
+// s' = sigma(V - eta).  With RES the partials hold sum ((s' - s) / dt)^2 over pore cells.
+template <bool RES>
+__global__ void __launch_bounds__(1024) k_nernst(NernstArgs a) {
+  const Grid g = a.g;
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z0 = blockIdx.z * a.zc;
+  const int z1 = min(z0 + a.zc, g.nz);
+  const long long pl = (long long)g.nx * g.ny;
+  double acc[NV] = {0, 0, 0, 0};
+  if (x < g.nx && y < g.ny && z0 < z1) {
+    long long i = x + (long long)g.nx * (y + (long long)g.ny * z0);
+    Cell<double> q;
+    double s_c = a.s[i];
+    double s_dn = z0 > 0 ? a.s[i - pl] : 0.0;
+    double wz_c = a.w.wz[i];
+    for (int z = z0; z < z1; ++z, i += pl) {
+      const bool up = z + 1 < g.nz;
+      const double s_up = up ? a.s[i + pl] : 0.0;
+      const double wz_u = up ? a.w.wz[i + pl] : 0.0;
+      const uint8_t f = a.flags[i];
+      double out = 0.0;
+      if (f & FL_PORE) {
+        q.c = s_c;
+        q.zm = s_dn;
+        q.zp = s_up;
+        q.wzm = wz_c;
+        q.wzp = wz_u;
+        q.gzm = (z > 0 && !(f & FL_ZM)) ? 1.0 : 0.0;
+        q.gzp = (up && !(f & FL_ZP)) ? 1.0 : 0.0;
+        load_plane<double>(q, a.s, a.w, f, g, x, y, z, i, a.s_in, true);
+        const double r = residual<double>(q, 0.0, 0.0);
+        out = s_c + a.dt * r;
+        const int nf = __popc((unsigned)(f & FL_FIBRE));
+        if (nf > 0) {
+          const double c = a.Da * (a.kappa ? (double)a.kappa[i] : 1.0) * (double)nf / a.K;
+          const double eta_i = 2.0 * asinh(-r / (2.0 * c * sqrt(s_c * (1.0 - s_c))));
+          const double eta = (1.0 - a.omega) * a.eta[i] + a.omega * eta_i;
+          a.eta[i] = eta;
+          out = 1.0 / (1.0 + exp(eta - a.V));
+        }
+        if (RES) {
+          const double d = (out - s_c) / a.dt;
+          acc[0] += d * d;
+          if (!isfinite(d)) acc[1] += 1.0;
+        }
+      }
+      a.s_new[i] = out;
+      s_dn = s_c;
+      s_c = s_up;
+      wz_c = wz_u;
+    }
+  }
+  if (RES) block_store<NV>(acc, 0u, a.partial + (long long)NV * (blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)));
+}
+
+void launch_nernst(const NernstArgs &a, const Tiles &t, hipStream_t st) {
+  dim3 grid = sweep_grid(a.g, t), block(64, t.ty, 1);
+  if (a.partial) k_nernst<true><<<grid, block, 0, st>>>(a);
+  else k_nernst<false><<<grid, block, 0, st>>>(a);
+}
+
+// ------------------------------------------------------------------------------------
 // Iterative upsampling: the problem coarsened by two in every direction, and the
 // prolongation of its steady state (converge on the unrefined grid, then start the refined
 // problem from the interpolated state; Sec. "Incompressible Fluid Flow")

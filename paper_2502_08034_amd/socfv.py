@@ -69,6 +69,7 @@ def _load():
                                         C.POINTER(Stats), P]),
         "socfv_batch_solve": (i, [i, PP, C.POINTER(Params), PP, C.POINTER(Stats), P]),
         "socfv_coarsen": (i, [P, P, P, P, P, P]),
+        "socfv_solve_nernst": (i, [P, C.POINTER(Params), d, P, P, C.POINTER(Stats), P]),
         "socfv_solve_soc_upsampled": (i, [P, C.POINTER(Params), P, C.POINTER(Stats),
                                           C.POINTER(Stats), P]),
         "socfv_set_tiles": (i, [P, i, i, i, i]),
@@ -237,6 +238,17 @@ def batch_solve(ctxs, ps, want_states=True):
     code = _lib.socfv_batch_solve(n, hs, pa, outs, sts, _stream())
     _check(code)
     return states, list(sts)
+
+
+def solve_nernst(ctx: Context, p: Params, omega=0.05, want_state=True, want_eta=False):
+    """Explicit Nernst model (FP64).  Returns (s or None, eta or None, stats)."""
+    s = torch.empty(ctx.shape, dtype=torch.float64, device="cuda") if want_state else None
+    eta = torch.empty(ctx.shape, dtype=torch.float64, device="cuda") if want_eta else None
+    st = Stats()
+    code = _lib.socfv_solve_nernst(ctx.handle, C.byref(p), float(omega), _ptr(s, torch.float64),
+                                   _ptr(eta, torch.float64), C.byref(st), _stream())
+    _check(code)
+    return s, eta, st
 
 
 def coarsen(ctx: Context):
