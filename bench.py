@@ -165,6 +165,47 @@ def cpu_baseline(geo, u_np, seconds):
                       f"({el:.1f} s); per-sweep rate, not run to steady state"}
 
 
+def logpile_sweep(sv, torch, pes, volts=(-2.0, 0.0, 2.0), s_in=1.7e-7):
+    """Voltage x flow-rate sweep on the logpile lattice (h = 1.25 um, 1024 x 512 x 128):
+    one batched FP32 solve of every (V, Pe) problem to residual 1e-8; s_eq = sigma(V),
+    Da = 0.45 cosh(V / 2), the paper's inlet SOC."""
+    from paper_2502_08034_amd import inputs as I
+    t = time.time()
+    g = I.logpile(1.25)
+    u, info = I.darcy_velocity(g.solid, 1.0, device="cuda", return_info=True, log=log,
+                               as_numpy=False)
+    log(f"logpile {g.solid.shape[::-1]}, porosity {g.porosity:.4f}, Darcy {info['cg_iterations']} "
+        f"iterations, {time.time() - t:.1f}s")
+    t = time.time()
+    pbs = {V: sv.Problem.create(g.solid, *u) for V in volts}
+    log(f"{len(volts)} contexts in {time.time() - t:.1f}s")
+    n = g.solid.size
+    table, total, sweeps = {}, 0.0, 0
+    # one batch per flow rate (problems of one flow rate need similar sweep counts)
+    for pe in pes:
+        params = [sv.params(precision="fp32", tol=1e-8, s_in=s_in, **I.voltage_params(V))
+                  for V in volts]
+        for V in volts:
+            pbs[V].set_flow_rate(pe)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, stats = sv.batch_solve([pbs[V].ctx for V in volts], params, want_states=False)
+        torch.cuda.synchronize()
+        mk = time.perf_counter() - t
+        total += mk
+        k = sum(st.iterations for st in stats)
+        sweeps += k
+        for V, st in zip(volts, stats):
+            table[f"V={V:+g},Pe={pe:g}"] = {"U": st.U, "sweeps": st.iterations,
+                                            "status": st.status}
+        log(f"Pe {pe}: batch of {len(volts)} in {mk:.1f}s, {k} sweeps, "
+            f"{k * n / mk / 1e9:.1f} GLUPS; U " + ", ".join(f"{st.U:.6f}" for st in stats))
+    print(json.dumps({"metric": "logpile voltage x flow sweep (batched per flow rate)",
+                      "problems": len(volts) * len(pes), "cells": n, "seconds": total,
+                      "sweeps": sweeps, "glups": sweeps * n / total / 1e9,
+                      "porosity": g.porosity, "s_in": s_in, "results": table}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +218,9 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-upsampling", action="store_true")
+    ap.add_argument("--logpile-sweep", action="store_true",
+                    help="voltage x flow-rate sweep on the 1024x512x128 logpile lattice through "
+                         "the batched solve (prints its own JSON line and exits)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--tiles", default=None, help="tile_y,z_chunk for the sweeps")
@@ -203,6 +247,9 @@ def main():
         torch.cuda.synchronize()
         del a, c
     pes = [float(v) for v in args.peclet.split(",")]
+    if args.logpile_sweep:
+        logpile_sweep(sv, torch, pes)
+        return
     geo, u1, cfg = build_slab(parse_scale(args.scale), "cuda")
     nz, ny, nx = geo.solid.shape
     ncell = nx * ny * nz

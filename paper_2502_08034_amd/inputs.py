@@ -42,7 +42,7 @@ import numpy as np
 __all__ = [
     "Geometry", "fibres_nonoverlap", "fibres_boolean", "fill_disconnected",
     "darcy_velocity", "lognormal_activity", "plug_flow_case", "workload",
-    "batch_workloads", "WORKLOADS",
+    "batch_workloads", "WORKLOADS", "logpile", "voltage_params",
 ]
 
 
@@ -324,6 +324,44 @@ def plug_flow_case(nx, ny, nz, u):
 # Named workloads (sizes of the paper-derived benchmark configurations)
 # ---------------------------------------------------------------------------------
 
+def logpile(h_um=1.25) -> Geometry:
+    """The logpile lattice of Sec. "Incompressible Flow Simulation for a Logpile Lattice":
+    a 1280 x 640 x 160 um box with 43 rods of diameter 20 um in seven layers at z = 20, 40,
+    ..., 140 um; odd layers run along x (four rods, 128 um apart in y), even layers along y
+    (nine rods, 128 um apart in x).  Voxel size h_um (1.25 um: 1024 x 512 x 128); a voxel is
+    fibre when its centre is strictly inside a rod.  Flow enters at x = 0."""
+    nx, ny, nz = int(round(1280 / h_um)), int(round(640 / h_um)), int(round(160 / h_um))
+    xc = (np.arange(nx) + 0.5) * h_um
+    yc = (np.arange(ny) + 0.5) * h_um
+    zc = (np.arange(nz) + 0.5) * h_um
+    r = 10.0
+    solid = np.zeros((nz, ny, nx), dtype=bool)
+    n = 0
+    for layer in range(7):
+        z0 = 20.0 * (layer + 1)
+        dz2 = (zc - z0) ** 2
+        if layer % 2 == 0:                       # along x, spaced in y
+            for yr in np.arange(1, 5) * 128.0:
+                m = (dz2[:, None] + (yc[None, :] - yr) ** 2) < r * r
+                solid |= m[:, :, None]
+                n += 1
+        else:                                    # along y, spaced in x
+            for xr in np.arange(1, 10) * 128.0:
+                m = (dz2[:, None] + (xc[None, :] - xr) ** 2) < r * r
+                solid |= m[:, None, :]
+                n += 1
+    geo = Geometry(solid.astype(np.uint8), r / h_um, n, 0.0,
+                   info={"kind": "logpile", "h_um": h_um})
+    return fill_disconnected(geo)
+
+
+def voltage_params(V, Da0=0.45):
+    """Reaction parameters at dimensionless voltage V for the affine rate at alpha = 1/2:
+    s_eq = sigma(V) (Eq. (seq-from-Var)) and Da = Da0 K(V) / K(0) with K = 2 cosh(V / 2), Da0
+    the per-face Damkohler number at V = 0 (0.45: the paper's k0, D and h = 1.25 um)."""
+    return {"s_eq": float(1.0 / (1.0 + np.exp(-V))), "Da": float(Da0 * np.cosh(V / 2.0))}
+
+
 WORKLOADS = {
     # 64x32x32, r = 3, porosity 0.85, cell Peclet 0.5
     "fibre64": dict(shape=(64, 32, 32), radius=3.0, porosity=0.85, peclet=0.5, seed=1,
@@ -334,6 +372,9 @@ WORKLOADS = {
     # paper-scale slab 1024x512x256 at h = 1.25 um, r = 4, porosity 0.78, Pe 0.2 / 1 / 5
     "slab1024": dict(shape=(1024, 512, 256), radius=4.0, porosity=0.78,
                      peclet=(0.2, 1.0, 5.0), seed=3, kind="boolean"),
+    # the paper's logpile lattice at h = 1.25 um (1024 x 512 x 128), Pe 0.2 / 1 / 5
+    "logpile": dict(shape=(1024, 512, 128), radius=8.0, peclet=(0.2, 1.0, 5.0), seed=0,
+                    kind="logpile"),
 }
 
 
@@ -344,7 +385,9 @@ def workload(name, device=None, rtol=1e-12, log=None, with_velocity=True, scale=
     """
     cfg = dict(WORKLOADS[name])
     nx, ny, nz = scale if scale is not None else cfg["shape"]
-    if cfg["kind"] == "nonoverlap":
+    if cfg["kind"] == "logpile":
+        geo = logpile(1.25 * cfg["shape"][0] / nx)
+    elif cfg["kind"] == "nonoverlap":
         geo = fibres_nonoverlap(nx, ny, nz, cfg["radius"], cfg["porosity"], cfg["seed"])
     else:
         geo = fibres_boolean(nx, ny, nz, cfg["radius"], cfg["porosity"], cfg["seed"])
