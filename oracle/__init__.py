@@ -22,6 +22,8 @@ Functions (each cites what it follows; the discretisation is described at the to
   by a sparse direct or Krylov solve of the same rows
 * ``adjoint`` / ``gradients``             explicit iteration for A^T psi = g and the
   design gradients dU/dkappa, dU/dln q
+* ``oracle.stokes``                       the upstream flow step: steady Stokes flow on
+  the voxel grid and the projection step of the Algorithm "Flow Simulation"
 * ``rate_*``                              the reaction-rate algebra of
   Eqs. (rate-soc-eta), (rate-from-soc), (rate-from-soc-gen), (seq-from-Var)
 """
