@@ -249,6 +249,55 @@ int socfv_solve_soc_upsampled(socfv_ctx *c, const socfv_params *p, double *s_out
                               socfv_stats *st, socfv_stats *coarse_st, void *hip_stream);
 
 /*
+ * Upstream flow step: the steady velocity field this solve takes as input, from the
+ * incompressible flow equations (Eqs. (navier-stokes), (incompressibility)) in the Stokes
+ * regime of Eq. (stokes-flow), by the projection method of Eqs. (cp1)-(cp4) (Algorithm "Flow
+ * Simulation", explicit momentum diffusion; momentum advection omitted), to the stop rule of
+ * Eq. (flow-cnvg).  Nondimensional: h = rho = mu = 1; the field is linear in p_in, so one
+ * solve serves every applied pressure (scale it with q in socfv_set_velocity).
+ *
+ * Discretisation: normal velocity on open faces (both cells pore, or the inlet / outlet face
+ * of a pore cell); pressure in pore cells; pressure p_in at the inlet face x = 0 and 0 at the
+ * outlet face x = nx; no-slip on fibre voxel faces and on the y / z walls (zero normal
+ * velocity; tangential wall on the voxel face); zero normal gradient of the velocity across
+ * the inlet and outlet planes.  Each step: u* = u + dt L u; (-D G) p = D gbc - D u* / dt by
+ * Jacobi-preconditioned CG from the previous pressure, stopped when dt ||r|| < cg_theta x the
+ * previous step's ||u' - u|| or after cg_max iterations; u' = u* - dt (G p + gbc).  The fixed
+ * point is the discrete Stokes solution (L u = G p on open faces, D u = 0 on pore cells)
+ * whatever cg_theta.  dt = cfl / 24 (Eq. (time-step-flow) with C_V = 6, C_A = C_F = 0).
+ *
+ *   p_in        applied inlet pressure (outlet at 0)
+ *   cfl         C_CFL, in (0, 4) (explicit diffusion is stable below 4); paper value 0.5
+ *   tol         eps_flow of Eq. (flow-cnvg): stop when ||u' - u||_2 < tol ||u'||_2 (1e-9)
+ *   cg_theta    pressure CG stop factor (0.1)
+ *   max_steps, check_every   step cap; steps between host checks of the stop rule
+ *   cg_max      cap on CG iterations per step
+ *
+ * ux, uy, uz: device, FP64, the staggered layout of socfv_set_velocity, written with the
+ * flow (closed faces 0); they also serve as the iteration's velocity, so they hold the last
+ * iterate on NOT_CONVERGED or DIVERGED.  p_out (nullable): device, FP64 (nz, ny, nx), the
+ * pressure (0 in fibre cells).  Needs a context from socfv_setup_geometry (velocity not
+ * needed).  Temporary device memory (~72 B per cell) is allocated and freed inside the call.
+ * Returns OK, NOT_CONVERGED (outputs written), DIVERGED, INVALID_ARG, HIP_ERROR or OOM.
+ */
+typedef struct {
+  double p_in, cfl, tol, cg_theta;
+  long max_steps;
+  int check_every, cg_max;
+} socfv_flow_params;
+typedef struct {
+  long steps, cg_iterations;
+  double change;       /* final ||u' - u|| / ||u'|| */
+  double divergence;   /* max over pore cells of |D u| */
+  double Q, Q_out;     /* flow rate through the inlet / outlet plane */
+  double u_max, dt, seconds;
+  int status;
+} socfv_flow_stats;
+void socfv_default_flow_params(socfv_flow_params *p);
+int socfv_solve_stokes(socfv_ctx *c, const socfv_flow_params *p, double *ux, double *uy,
+                       double *uz, double *p_out, socfv_flow_stats *st, void *hip_stream);
+
+/*
  * Launch shapes.  Single sweeps work on (64 x tile_y) lanes marching z_chunk cells along z;
  * with two_sweeps set (the default), FP32 sweeps on grids with even nx run two sweeps per
  * launch on 64 x 16 lanes marching z_chunk2 cells.  socfv_set_tiles overrides them for a

@@ -1478,4 +1478,141 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
   return rc;
 }
 
+void socfv_default_flow_params(socfv_flow_params *p) {
+  if (!p) return;
+  p->p_in = 1.0;
+  p->cfl = 0.5;
+  p->tol = 1e-9;
+  p->cg_theta = 0.1;
+  p->max_steps = 10000000L;
+  p->check_every = 50;
+  p->cg_max = 256;
+}
+
+int socfv_solve_stokes(socfv_ctx *c, const socfv_flow_params *p, double *ux, double *uy,
+                       double *uz, double *p_out, socfv_flow_stats *st, void *hip_stream) {
+  const double t0 = now_s();
+  if (!c) return fail(SOCFV_INVALID_ARG, "NULL context");
+  if (!p) return fail(SOCFV_INVALID_ARG, "params is NULL");
+  if (!ux || !uy || !uz) return fail(SOCFV_INVALID_ARG, "NULL velocity buffer");
+  if (!(p->cfl > 0.0 && p->cfl < 4.0))
+    return fail(SOCFV_INVALID_ARG, "cfl must be in (0, 4) (explicit diffusion stability)");
+  if (!(p->tol >= 0.0) || !(p->cg_theta > 0.0) || !std::isfinite(p->p_in))
+    return fail(SOCFV_INVALID_ARG, "tol >= 0, cg_theta > 0 and a finite p_in are required");
+  if (p->max_steps < 1 || p->check_every < 1 || p->cg_max < 1)
+    return fail(SOCFV_INVALID_ARG, "max_steps, check_every and cg_max must be >= 1");
+  const Grid &g = c->g;
+  const long long n = g.n;
+  const long long nf[3] = {(long long)(g.nx + 1) * g.ny * g.nz,
+                           (long long)g.nx * (g.ny + 1) * g.nz,
+                           (long long)g.nx * g.ny * (g.nz + 1)};
+  FlowArgs a{};
+  a.g = g;
+  a.flags = c->flags;
+  a.u[0] = ux; a.u[1] = uy; a.u[2] = uz;
+  a.nbc = flow_cell_blocks(g);
+  a.nbf = flow_face_blocks(g);
+  // Eq. (time-step-flow) with C_V = 2 mu / rho * 3 / h^2 = 6 and no advective or force term
+  a.dt = 0.5 * p->cfl / (2.0 * 6.0);
+  a.p_in = p->p_in;
+  a.theta2 = p->cg_theta * p->cg_theta;
+  std::vector<void *> mem;
+  auto alloc = [&](void **ptr, size_t bytes) -> int {
+    HIPCHK(hipMalloc(ptr, bytes));
+    mem.push_back(*ptr);
+    return 0;
+  };
+  const int rc = [&]() -> int {
+    for (int k = 0; k < 3; ++k) {
+      TRY(alloc((void **)&a.code[k], sizeof(uint16_t) * (size_t)nf[k]));
+      TRY(alloc((void **)&a.us[k], sizeof(double) * (size_t)nf[k]));
+    }
+    double **cellv[6] = {&a.p, &a.r, &a.z, &a.q, &a.d[0], &a.d[1]};
+    for (double **v : cellv) TRY(alloc((void **)v, sizeof(double) * (size_t)n));
+    const long long npart = 5ll * a.nbc + 6ll * a.nbf + 4ll * a.nbc + FS_N;
+    double *part = nullptr;
+    TRY(alloc((void **)&part, sizeof(double) * (size_t)npart));
+    a.prz[0] = part;
+    a.prz[1] = part + a.nbc;
+    a.prr[0] = part + 2ll * a.nbc;
+    a.prr[1] = part + 3ll * a.nbc;
+    a.pdq = part + 4ll * a.nbc;
+    a.pdu = part + 5ll * a.nbc;
+    a.pdiv = a.pdu + 6ll * a.nbf;
+    a.sc = a.pdiv + 4ll * a.nbc;
+    TRY(enter(c, hip_stream));
+    // start from rest with zero pressure; zero partials make the first step's CG run to
+    // its cap
+    for (int k = 0; k < 3; ++k) launch_fill_f64(a.u[k], nf[k], 0.0, c->st);
+    for (double **v : cellv) launch_fill_f64(*v, n, 0.0, c->st);
+    launch_fill_f64(part, npart, 0.0, c->st);
+    launch_flow_codes(a, c->st);
+    HIPCHK(hipGetLastError());
+    long steps = 0;
+    double total_prev = 0.0, du = INFINITY, un = 0.0;
+    int m = p->cg_max;
+    int status = SOCFV_NOT_CONVERGED;
+    while (steps < p->max_steps) {
+      const long k = std::min<long>(p->check_every, p->max_steps - steps);
+      for (long s = 0; s < k; ++s) {
+        launch_flow_predict(a, c->st);
+        launch_flow_cg_init(a, c->st);
+        for (int j = 0; j < m; ++j) launch_flow_cg_iter(a, j, c->st);
+        launch_flow_project(a, c->st);
+      }
+      HIPCHK(hipGetLastError());
+      launch_reduce(a.pdu, 3 * a.nbf, 2, 0u, c->dres, c->st);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(c->hres, c->dres, sizeof(double) * 2, hipMemcpyDeviceToHost, c->st));
+      HIPCHK(hipMemcpyAsync(c->hres + 2, a.sc + FS_CG_TOTAL, sizeof(double),
+                            hipMemcpyDeviceToHost, c->st));
+      HIPCHK(hipStreamSynchronize(c->st));
+      steps += k;
+      du = std::sqrt(c->hres[0]);
+      un = std::sqrt(c->hres[1]);
+      const double total = c->hres[2];
+      if (!std::isfinite(du) || !std::isfinite(un))
+        return fail(SOCFV_DIVERGED, "flow steps diverged at step %ld", steps);
+      // launch enough CG iterations for this phase: three times the recent average, at
+      // least 8 (kernels past the stop return at once)
+      const double avg = (total - total_prev) / (double)k;
+      total_prev = total;
+      m = std::min(p->cg_max, std::max(8, (int)std::ceil(3.0 * avg) + 8));
+      if (un > 0.0 && du < p->tol * un) {
+        status = SOCFV_OK;
+        break;
+      }
+    }
+    launch_flow_check(a, c->st);
+    HIPCHK(hipGetLastError());
+    launch_reduce(a.pdiv, a.nbc, 4, 0x5u, c->dres, c->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(c->hres, c->dres, sizeof(double) * 4, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(c->hres + 4, a.sc + FS_CG_TOTAL, sizeof(double),
+                          hipMemcpyDeviceToHost, c->st));
+    if (p_out)
+      HIPCHK(hipMemcpyAsync(p_out, a.p, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice,
+                            c->st));
+    TRY(leave(c, hip_stream));
+    socfv_flow_stats s{};
+    s.steps = steps;
+    s.cg_iterations = (long)c->hres[4];
+    s.change = un > 0.0 ? du / un : INFINITY;
+    s.divergence = c->hres[0];
+    s.Q = c->hres[1];
+    s.u_max = c->hres[2];
+    s.Q_out = c->hres[3];
+    s.dt = a.dt;
+    s.status = status;
+    s.seconds = now_s() - t0;
+    if (st) *st = s;
+    if (status == SOCFV_NOT_CONVERGED)
+      fail(status, "flow not converged after %ld steps (relative change %g)", steps, s.change);
+    return status;
+  }();
+  if (rc < 0 && c->st) (void)hipStreamSynchronize(c->st);
+  for (void *ptr : mem) hfree(ptr);
+  return rc;
+}
+
 }  // extern "C"

@@ -156,6 +156,37 @@ struct NernstArgs {
 };
 void launch_nernst(const NernstArgs &a, const Tiles &t, hipStream_t st);
 
+// ---- upstream flow step: steady Stokes flow by projection steps (flow.hip) ------------
+// Face arrays in the staggered layout (x faces (nz, ny, nx+1), y faces (nz, ny+1, nx),
+// z faces (nz+1, ny, nx)).  code[a][f]: bit 15 = open face; bits 2n..2n+1 = class of the
+// neighbour face n (x-, x+, y-, y+, z-, z+) of the same orientation: 0 beyond the inlet /
+// outlet plane (zero gradient), 1 open, 2 closed along the face normal, 3 wall across it.
+constexpr uint16_t FC_OPEN = 0x8000;
+// Scalar slots of the flow step (device doubles after the partials)
+enum FlowSlot { FS_TARGET = 0, FS_DONE = 1, FS_CG_STEP = 2, FS_CG_TOTAL = 3, FS_N = 4 };
+struct FlowArgs {
+  Grid g;
+  const uint8_t *flags;
+  uint16_t *code[3];
+  double *u[3];          // velocity (updated in place by the projection)
+  double *us[3];         // predictor output u*
+  double *p, *r, *z, *q, *d[2];   // pressure and CG vectors (cells)
+  double dt, p_in, theta2;        // theta2: (CG stop factor)^2
+  int nbc, nbf;          // blocks of the cell kernels / per face array of the face kernels
+  double *prz[2], *prr[2], *pdq;  // per-block CG partials (cell kernels), ping-pong by parity
+  double *pdu;           // per-block [sum du^2, sum u^2] of the projection, (3 nbf) x 2
+  double *pdiv;          // per-block [max |div u|, inlet flux] (cell kernels), nbc x 2
+  double *sc;            // FlowSlot scalars
+};
+int flow_cell_blocks(const Grid &g);
+int flow_face_blocks(const Grid &g);
+void launch_flow_codes(const FlowArgs &a, hipStream_t st);
+void launch_flow_predict(const FlowArgs &a, hipStream_t st);
+void launch_flow_cg_init(const FlowArgs &a, hipStream_t st);
+void launch_flow_cg_iter(const FlowArgs &a, int j, hipStream_t st);   // both CG kernels
+void launch_flow_project(const FlowArgs &a, hipStream_t st);
+void launch_flow_check(const FlowArgs &a, hipStream_t st);   // fills pdiv
+
 
 dim3 sweep_grid(const Grid &g, const Tiles &t);
 // FP32 sweeps use four cells per lane when nx % 4 == 0 (grid: 256 x cells per block)

@@ -44,6 +44,22 @@ class Stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class FlowParams(C.Structure):
+    _fields_ = [("p_in", C.c_double), ("cfl", C.c_double), ("tol", C.c_double),
+                ("cg_theta", C.c_double), ("max_steps", C.c_long), ("check_every", C.c_int),
+                ("cg_max", C.c_int)]
+
+
+class FlowStats(C.Structure):
+    _fields_ = [("steps", C.c_long), ("cg_iterations", C.c_long), ("change", C.c_double),
+                ("divergence", C.c_double), ("Q", C.c_double), ("Q_out", C.c_double),
+                ("u_max", C.c_double), ("dt", C.c_double), ("seconds", C.c_double),
+                ("status", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class SocfvError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{_NAMES.get(code, code)}: {msg}")
@@ -72,6 +88,9 @@ def _load():
         "socfv_solve_nernst": (i, [P, C.POINTER(Params), d, P, P, C.POINTER(Stats), P]),
         "socfv_solve_soc_upsampled": (i, [P, C.POINTER(Params), P, C.POINTER(Stats),
                                           C.POINTER(Stats), P]),
+        "socfv_default_flow_params": (None, [C.POINTER(FlowParams)]),
+        "socfv_solve_stokes": (i, [P, C.POINTER(FlowParams), P, P, P, P,
+                                   C.POINTER(FlowStats), P]),
         "socfv_set_tiles": (i, [P, i, i, i, i]),
         "socfv_autotune": (i, [P, i, C.POINTER(C.c_int), P]),
         "socfv_info": (i, [P, C.POINTER(C.c_int), C.POINTER(C.c_long)]),
@@ -249,6 +268,35 @@ def solve_nernst(ctx: Context, p: Params, omega=0.05, want_state=True, want_eta=
                                    _ptr(eta, torch.float64), C.byref(st), _stream())
     _check(code)
     return s, eta, st
+
+
+def flow_params(**kw) -> FlowParams:
+    """Flow-step parameters: library defaults overridden by keyword."""
+    fp = FlowParams()
+    _lib.socfv_default_flow_params(C.byref(fp))
+    for k, v in kw.items():
+        if not hasattr(fp, k):
+            raise AttributeError(f"unknown flow parameter {k}")
+        setattr(fp, k, v)
+    return fp
+
+
+def solve_stokes(ctx: Context, fp: FlowParams | None = None, want_pressure=False, **kw):
+    """Steady Stokes flow through the context's pore space (projection steps).  Returns
+    (ux, uy, uz, p or None, stats); float64 CUDA tensors in the staggered layout."""
+    fp = fp if fp is not None else flow_params(**kw)
+    nz, ny, nx = ctx.shape
+    dev = "cuda"
+    ux = torch.empty((nz, ny, nx + 1), dtype=torch.float64, device=dev)
+    uy = torch.empty((nz, ny + 1, nx), dtype=torch.float64, device=dev)
+    uz = torch.empty((nz + 1, ny, nx), dtype=torch.float64, device=dev)
+    pr = torch.empty((nz, ny, nx), dtype=torch.float64, device=dev) if want_pressure else None
+    st = FlowStats()
+    code = _lib.socfv_solve_stokes(ctx.handle, C.byref(fp), _ptr(ux, torch.float64),
+                                   _ptr(uy, torch.float64), _ptr(uz, torch.float64),
+                                   _ptr(pr, torch.float64), C.byref(st), _stream())
+    _check(code)
+    return ux, uy, uz, pr, st
 
 
 def coarsen(ctx: Context):

@@ -43,3 +43,15 @@ def test_default_params_without_gpu():
     code = mod.lib().socfv_solve_soc_steady(None, ctypes.byref(p), None, None, ctypes.byref(st), None)
     assert code == mod.INVALID_ARG
     assert b"context" in mod.lib().socfv_last_error()
+
+
+def test_flow_params_without_gpu():
+    from paper_2502_08034_amd import socfv as mod
+    fp = mod.flow_params(cfl=2.0)
+    assert fp.p_in == 1.0 and fp.cfl == 2.0 and fp.tol == 1e-9 and fp.cg_theta == 0.1
+    assert fp.check_every == 50 and fp.cg_max == 256
+    st = mod.FlowStats()
+    code = mod.lib().socfv_solve_stokes(None, ctypes.byref(fp), None, None, None, None,
+                                        ctypes.byref(st), None)
+    assert code == mod.INVALID_ARG
+    assert b"context" in mod.lib().socfv_last_error()

@@ -1,0 +1,141 @@
+"""Upstream flow step on the GPU against the oracle (needs an MI355X).
+
+The projection steps reach the oracle's direct solve of the discrete Stokes problem; with the
+pressure solved to round-off each step they follow the oracle's projection iteration step
+for step; at larger sizes the field meets the residual bound that the stop rule implies; the
+field is exactly linear in the applied pressure; and it feeds the state-of-charge solve,
+which then agrees with the oracle's solve on the oracle's own flow field.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2502_08034_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sv():
+    from paper_2502_08034_amd import socfv
+    return socfv
+
+
+@pytest.fixture(scope="module")
+def ost():
+    from oracle import stokes
+    return stokes
+
+
+def geometry(kind, nx, ny, nz, seed=41):
+    if kind == "duct":
+        return np.zeros((nz, ny, nx), np.uint8)
+    return I.fibres_nonoverlap(nx, ny, nz, 2.5, 0.8, seed).solid
+
+
+def gpu_flow(sv, solid, **kw):
+    ctx = sv.setup_geometry(torch.as_tensor(solid, device="cuda"))
+    ux, uy, uz, p, st = sv.solve_stokes(ctx, want_pressure=True, **kw)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in (ux, uy, uz, p)], st
+
+
+@pytest.mark.parametrize("kind,shape", [("duct", (12, 7, 5)), ("fibres", (32, 16, 16)),
+                                        ("fibres", (37, 19, 13))])
+def test_steady_flow_matches_the_direct_solve(sv, ost, kind, shape):
+    solid = geometry(kind, *shape)
+    (ux, uy, uz, p), st = gpu_flow(sv, solid, cfl=2.0, tol=1e-12)
+    assert st.status == sv.OK
+    print(f"{kind} {shape}: {st.steps} steps, {st.cg_iterations} CG iterations, "
+          f"{st.seconds:.2f} s", flush=True)
+    ox, oy, oz, op = ost.stokes_steady(solid)
+    umax = np.abs(ox).max()
+    for got, want in ((ux, ox), (uy, oy), (uz, oz)):
+        assert np.abs(got - want).max() <= 1e-8 * umax
+    pore = solid == 0
+    assert np.abs(p - op)[pore].max() <= 1e-8
+    assert np.all(p[~pore] == 0)
+    assert st.divergence <= 1e-10 * umax
+    assert abs(st.Q - ost.flow_rate(ox)) <= 1e-8 * ost.flow_rate(ox)
+    assert abs(st.Q - st.Q_out) <= 1e-9 * st.Q
+
+
+def test_steps_follow_the_oracle_iteration(sv, ost):
+    """Pressure solved to round-off in every step: the GPU's steps are the oracle's."""
+    solid = geometry("fibres", 24, 14, 12, seed=42)
+    nsteps = 30
+    (ux, uy, uz, p), st = gpu_flow(sv, solid, cfl=2.0, tol=0.0, max_steps=nsteps,
+                                   check_every=10, cg_theta=1e-30, cg_max=400)
+    assert st.status == sv.NOT_CONVERGED and st.steps == nsteps
+    ops = ost.StokesOperators(solid)
+    dt = ost.flow_time_step(2.0)
+    assert abs(st.dt - dt) <= 1e-16
+    u = np.zeros(ops.nu)
+    pv = np.zeros(ops.np_)
+    for _ in range(nsteps):
+        u, pv = ost.chorin_step(ops, u, pv, dt)
+    ox, oy, oz, op = ops.unpack(u, pv)
+    umax = np.abs(ox).max()
+    for got, want in ((ux, ox), (uy, oy), (uz, oz)):
+        assert np.abs(got - want).max() <= 1e-10 * umax
+    assert np.abs(p - op).max() <= 1e-10
+
+
+def test_full_field_meets_the_stop_rule_bound(sv, ost):
+    """96 x 48 x 48 fibres at the default parameters (cfl 0.5, eps 1e-9): the momentum
+    residual of the returned (u, p) is at most ||u' - u|| (1 / dt + 12) <= eps ||u|| (1 / dt +
+    12), continuity holds to the CG stop, and inflow equals outflow."""
+    solid = I.fibres_nonoverlap(96, 48, 48, 3.0, 0.85, 43).solid
+    (ux, uy, uz, p), st = gpu_flow(sv, solid)
+    assert st.status == sv.OK
+    print(f"96x48x48: {st.steps} steps, {st.cg_iterations} CG iterations, {st.seconds:.2f} s",
+          flush=True)
+    unorm = np.sqrt(sum((a * a).sum() for a in (ux, uy, uz)))
+    mom, div, closed = ost.stokes_residual(solid, ux, uy, uz, p)
+    assert closed == 0.0
+    assert mom <= 1e-9 * unorm * (1.0 / st.dt + 12.0) * 1.01
+    assert div <= 1e-9 * unorm and st.divergence <= 1e-9 * unorm
+    assert abs(st.Q - st.Q_out) <= 1e-8 * st.Q
+
+
+def test_field_is_linear_in_the_applied_pressure(sv):
+    solid = geometry("fibres", 40, 20, 20, seed=44)
+    (a, _, _, pa), sa = gpu_flow(sv, solid, p_in=1.0, cfl=2.0, tol=1e-10)
+    (b, _, _, pb), sb = gpu_flow(sv, solid, p_in=2.0, cfl=2.0, tol=1e-10)
+    assert sa.steps == sb.steps and sa.cg_iterations == sb.cg_iterations
+    assert np.abs(b - 2.0 * a).max() <= 1e-14 * np.abs(b).max()
+    assert np.abs(pb - 2.0 * pa).max() <= 1e-14
+
+
+def test_flow_feeds_the_soc_solve(sv, ost, orc):
+    """Each side runs its own pipeline: GPU flow -> GPU solve, oracle flow -> oracle solve."""
+    solid = geometry("fibres", 32, 16, 16, seed=45)
+    ctx = sv.setup_geometry(torch.as_tensor(solid, device="cuda"))
+    ux, uy, uz, _, st = sv.solve_stokes(ctx, cfl=2.0, tol=1e-12)
+    assert st.status == sv.OK
+    # scale to cell Peclet 1: mean interstitial velocity (Q / (ny nz)) / porosity
+    phi = float((solid == 0).mean())
+    q = 1.0 / ((st.Q / (solid.shape[1] * solid.shape[0])) / phi)
+    sv.set_velocity(ctx, ux, uy, uz, q=q)
+    p = sv.params(precision="fp64", tol=1e-11, s_in=1.0, s_eq=0.0, Da=0.45)
+    _, gst = sv.solve_soc_steady(ctx, p, want_state=False)
+    assert gst.status == sv.OK
+    ox, oy, oz, _ = ost.stokes_steady(solid)
+    oq = 1.0 / ((ost.flow_rate(ox) / (solid.shape[1] * solid.shape[0])) / phi)
+    op = orc.Problem(solid, ox * oq, oy * oq, oz * oq, s_in=1.0, s_eq=0.0, Da=0.45)
+    Ux = orc.outputs(op, orc.exact_steady(op))["U"]
+    print(f"U (Stokes flow, Pe 1): GPU {gst.U:.10f}, oracle {Ux:.10f}", flush=True)
+    assert abs(gst.U - Ux) <= 1e-8 * abs(Ux)
+
+
+def test_flow_error_paths(sv):
+    solid = geometry("fibres", 16, 8, 8, seed=46)
+    ctx = sv.setup_geometry(torch.as_tensor(solid, device="cuda"))
+    for kw in (dict(cfl=4.0), dict(cfl=0.0), dict(cg_theta=0.0), dict(max_steps=0),
+               dict(p_in=float("nan"))):
+        with pytest.raises(sv.SocfvError) as e:
+            sv.solve_stokes(ctx, **kw)
+        assert e.value.code == sv.INVALID_ARG
+    # a step cap short of convergence returns NOT_CONVERGED with the last iterate
+    ux, uy, uz, _, st = sv.solve_stokes(ctx, max_steps=20, check_every=20)
+    assert st.status == sv.NOT_CONVERGED and st.steps == 20 and st.Q > 0
