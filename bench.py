@@ -206,6 +206,42 @@ def logpile_sweep(sv, torch, pes, volts=(-2.0, 0.0, 2.0), s_in=1.7e-7):
                       "porosity": g.porosity, "s_in": s_in, "results": table}), flush=True)
 
 
+def stokes_flow(sv, torch, name="fibre256", cfl=0.5, tol=1e-9, max_steps=10**7, scale=None):
+    """Upstream flow step on a fibre workload: steady Stokes flow from rest by projection
+    steps at the paper's C_CFL = 1/2 and eps_flow = 1e-9, then the SOC solve on that flow."""
+    from paper_2502_08034_amd import inputs as I
+    w = I.workload(name, with_velocity=False, scale=scale)
+    solid = w["solid"]
+    nz, ny, nx = solid.shape
+    n = solid.size
+    phi = float((solid == 0).mean())
+    ctx = sv.setup_geometry(torch.as_tensor(solid, device="cuda"))
+    sv.solve_stokes(ctx, cfl=cfl, max_steps=10, check_every=10)       # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ux, uy, uz, _, st = sv.solve_stokes(ctx, cfl=cfl, tol=tol, max_steps=max_steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    log(f"Stokes flow {nx}x{ny}x{nz}: {st.steps} steps, {st.cg_iterations} CG iterations "
+        f"({st.cg_iterations / st.steps:.1f} per step), {el:.2f}s, change {st.change:.2e}, "
+        f"max |div u| / max |u| {st.divergence / st.u_max:.2e}")
+    out = {"metric": "steady Stokes flow by projection steps", "workload": name,
+           "shape": [nx, ny, nz], "cells": n, "porosity": phi, "cfl": cfl, "tol": tol,
+           "status": st.status, "steps": st.steps, "cg_iterations": st.cg_iterations,
+           "seconds": el, "ms_per_step": 1e3 * el / st.steps,
+           "cell_steps_per_s": n * st.steps / el, "change": st.change,
+           "divergence_rel": st.divergence / st.u_max, "Q": st.Q, "Q_out": st.Q_out}
+    if st.status == sv.OK:
+        # the SOC solve on this flow at cell Peclet 1 (mean interstitial velocity)
+        q = 1.0 / ((st.Q / (ny * nz)) / phi)
+        sv.set_velocity(ctx, ux, uy, uz, q=q)
+        _, sst = sv.solve_soc_steady(ctx, sv.params(precision="fp32", tol=1e-8),
+                                     want_state=False)
+        out["soc_pe1"] = {"U": sst.U, "sweeps": sst.iterations, "status": sst.status}
+        log(f"SOC solve on the Stokes flow at Peclet 1: U {sst.U:.6f}, {sst.iterations} sweeps")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +257,11 @@ def main():
     ap.add_argument("--logpile-sweep", action="store_true",
                     help="voltage x flow-rate sweep on the 1024x512x128 logpile lattice through "
                          "the batched solve (prints its own JSON line and exits)")
+    ap.add_argument("--stokes-flow", action="store_true",
+                    help="upstream flow step: steady Stokes flow on the 256x128x128 fibre "
+                         "workload (prints its own JSON line and exits)")
+    ap.add_argument("--flow-cfl", type=float, default=0.5)
+    ap.add_argument("--flow-max-steps", type=int, default=10**7)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--tiles", default=None, help="tile_y,z_chunk for the sweeps")
@@ -249,6 +290,10 @@ def main():
     pes = [float(v) for v in args.peclet.split(",")]
     if args.logpile_sweep:
         logpile_sweep(sv, torch, pes)
+        return
+    if args.stokes_flow:
+        stokes_flow(sv, torch, cfl=args.flow_cfl, max_steps=args.flow_max_steps,
+                    scale=parse_scale(args.scale))
         return
     geo, u1, cfg = build_slab(parse_scale(args.scale), "cuda")
     nz, ny, nx = geo.solid.shape
