@@ -17,7 +17,8 @@
  *
  *   face class                    upwind value        diffusive coefficient G_f
  *   interior (pore both sides)    s of the neighbour  1
- *   inlet  (x- face of x = 0)     s_in                2   (Dirichlet value on the face)
+ *   inlet  (x- face of x = 0)     s_in (s_P where     2   (Dirichlet value on the face)
+ *                                 the flow leaves)
  *   outlet (x+ face of x = nx-1)  s_P                 0   (no concentration gradient)
  *   fibre face, y/z domain wall   no flux             0   (w_f must be 0)
  *
@@ -419,7 +420,8 @@ void orc_iterate(int nx, int ny, int nz, const uint8_t *solid, const double *ux,
  * out[0] U         = (sbar_out - s_in) / (s_eq - s_in)
  * out[1] sbar_out  = sum_outlet w s_P / sum_outlet w
  * out[2] F_in      = total (advective + diffusive) flux of s entering through the inlet
- * out[3] F_in_adv  = advective part only, sum_inlet u_x s_in (electron-flow definition)
+ * out[3] F_in_adv  = advective part only, sum_inlet u_x s_up (electron-flow definition;
+ *                    s_up = s_in where u_x > 0, s_P where the flow leaves through the inlet)
  * out[4] F_out     = sum_outlet w s_P
  * out[5] reaction  = sum_P lam_P (s_P - s_eq)          (finite rate), or
  *                    sum over held cells of T_P (pinned), T_P = R_P without the
@@ -436,9 +438,11 @@ void orc_outputs(int nx, int ny, int nz, const uint8_t *solid, const double *ux,
         for (long y = 0; y < ny; ++y) {
             long P0 = cidx(&p, 0, y, z), P1 = cidx(&p, nx - 1, y, z);
             if (!solid[P0]) {
+                /* upwind: inflow brings s_in, outflow through the inlet carries s_P */
                 double u = ux[(nx + 1) * (y + (long)ny * z)];
-                fin += u * s_in + 2.0 * (s_in - s[P0]);
-                fin_adv += u * s_in;
+                double adv = dmax(u, 0.0) * s_in + dmin(u, 0.0) * s[P0];
+                fin += adv + 2.0 * (s_in - s[P0]);
+                fin_adv += adv;
             }
             if (!solid[P1]) {
                 double w = ux[nx + (nx + 1) * (y + (long)ny * z)];
