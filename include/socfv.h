@@ -58,7 +58,7 @@ typedef enum {
   SOCFV_NOT_CONVERGED = 1,   /* max_iter reached; outputs are still written */
   SOCFV_INVALID_ARG = -1,
   SOCFV_BAD_GEOMETRY = -2,   /* pore cell not face-connected to the inlet, no inlet/outlet pore */
-  SOCFV_BAD_VELOCITY = -3,   /* non-finite, flux through a closed face, inlet backflow, Q <= 0,
+  SOCFV_BAD_VELOCITY = -3,   /* non-finite, flux through a closed face, Q <= 0,
                                 or divergence above the tolerance */
   SOCFV_DIVERGED = -4,       /* non-finite residual or s outside [min(s_in,s_eq), max(..)] */
   SOCFV_HIP_ERROR = -5,
@@ -130,8 +130,10 @@ int socfv_setup_geometry(socfv_ctx **out, int nx, int ny, int nz, const uint8_t 
  * Face velocities (device, FP64, staggered layout above), multiplied by q (the flow is
  * linear in the driving pressure in the Stokes regime, so one field serves every flow
  * rate).  Stored in FP32 and FP64.  Rejects (BAD_VELOCITY) non-finite values, non-zero
- * velocity on a face shared with a fibre voxel or on a y/z wall, backflow through the
- * inlet, no inflow, and a cell divergence above 1e-6 times the largest face velocity.
+ * velocity on a face shared with a fibre voxel or on a y/z wall, no net inflow (Q <= 0),
+ * and a cell divergence above 1e-6 times the largest face velocity.  Flow may leave through
+ * part of the inlet (a pressure-driven flow does so next to an obstacle near the inlet):
+ * such a face carries the cell's value out (upwind), its Dirichlet diffusion unchanged.
  */
 int socfv_set_velocity(socfv_ctx *c, const double *ux, const double *uy, const double *uz,
                        double q, void *hip_stream);

@@ -617,9 +617,8 @@ int socfv_set_velocity(socfv_ctx *c, const double *ux, const double *uy, const d
   c->have_velocity = false;
   c->have_state = false;
   if (v[3] > 0)
-    return fail(SOCFV_BAD_VELOCITY, "%.0f faces: non-finite, flux through a closed face or inlet "
-                "backflow", v[3]);
-  if (!(v[0] > 0)) return fail(SOCFV_BAD_VELOCITY, "no inflow (Q = %g)", v[0]);
+    return fail(SOCFV_BAD_VELOCITY, "%.0f faces: non-finite or flux through a closed face", v[3]);
+  if (!(v[0] > 0)) return fail(SOCFV_BAD_VELOCITY, "no net inflow (Q = %g)", v[0]);
   if (v[1] > 1e-6 * v[2])
     return fail(SOCFV_BAD_VELOCITY, "cell divergence %g exceeds 1e-6 x max velocity %g", v[1], v[2]);
   c->Q_in = v[0];

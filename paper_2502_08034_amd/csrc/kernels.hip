@@ -141,8 +141,9 @@ int velocity_blocks(const Grid &g) { return (int)((g.n + 255) / 256); }
 
 // One thread per cell: the cell's lower x / y / z faces, its outlet face (x = nx-1) and
 // its upper wall faces (y = ny-1, z = nz-1).  A face with a pore cell on one side and a
-// fibre voxel or a wall on the other must carry zero velocity; an inlet face must not
-// carry backflow.  Faces without a pore cell on either side are stored as zero.
+// fibre voxel or a wall on the other must carry zero velocity.  Inlet and outlet faces may
+// carry flow either way (upwinded like every face).  Faces without a pore cell on either
+// side are stored as zero.
 // partial per block: [Q_in, max|div|, max|u|, bad faces]
 __global__ void __launch_bounds__(256) k_velocity(Grid g, const uint8_t *__restrict__ flags,
                                                   const double *__restrict__ ux,
@@ -177,7 +178,6 @@ __global__ void __launch_bounds__(256) k_velocity(Grid g, const uint8_t *__restr
     if (!ox && (pore || pxm) && a != 0.0) bad += 1.0;
     if (!oy && (pore || pym) && b != 0.0) bad += 1.0;
     if (!oz && (pore || pzm) && c != 0.0) bad += 1.0;
-    if (x == 0 && pore && a < 0.0) bad += 1.0;       // inlet backflow
     if (!ox) a = 0.0;
     if (!oy) b = 0.0;
     if (!oz) c = 0.0;
@@ -1377,9 +1377,11 @@ __global__ void __launch_bounds__(256) k_outputs(Grid g, const uint8_t *__restri
         v[1] = wo;
       }
       if (x == 0) {
+        // upwind: inflow brings s_in, outflow through the inlet carries s_P
         const double u = w.wx[i];
-        v[2] = u * s_in + 2.0 * (s_in - q.c);
-        v[3] = u * s_in;
+        const double adv = fmax(u, 0.0) * s_in + fmin(u, 0.0) * q.c;
+        v[2] = adv + 2.0 * (s_in - q.c);
+        v[3] = adv;
       }
       if (held) {
         v[4] = residual<double>(q, 0.0, s_eq);        // absorbed by the electrode cell

@@ -1,9 +1,10 @@
 """Summaries of rocprofv3 CSV output for this library's kernels (a profiling aid: it only
 reads CSV files and prints markdown).
 
-``trace CSV``: dispatch count and duration statistics per (kernel, grid size) from a
-``--kernel-trace`` CSV, so that launches of one kernel on differently sized problems are not
-averaged together.
+``trace CSV [--split-us T]``: dispatch count and duration statistics per (kernel, grid size)
+from a ``--kernel-trace`` CSV, so that launches of one kernel on differently sized problems are
+not averaged together; with ``--split-us`` each group is split into dispatches of at least T us
+and shorter ones (kernels that return at once once a device-side stop is set).
 
 ``pmc --fetch CSV --write CSV [--sq CSV] --kernel NAME --cells N --updates U``: HBM bytes per
 launch of the kernel at its largest grid, from ``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``
@@ -37,17 +38,23 @@ def grid_of(row):
     return tuple(int(row[k]) for k in ("Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z") if k in row)
 
 
-def trace(path, match):
+def trace(path, match, split_us=None):
     groups = collections.defaultdict(list)
     with open(path) as f:
         for r in csv.DictReader(f):
             if match not in r["Kernel_Name"]:
                 continue
-            groups[(short(r["Kernel_Name"]), grid_of(r))].append(
-                int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+            dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            key = (short(r["Kernel_Name"]), grid_of(r))
+            if split_us is not None:
+                key += ("" if dur >= split_us * 1e3 else f"< {split_us:g} us",)
+            groups[key].append(dur)
     print("| kernel | grid | calls | total ms | avg us | median us | min us | max us |")
     print("|---|---|---|---|---|---|---|---|")
-    for (k, g), v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+    for key, v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        k, g = key[0], key[1]
+        if len(key) > 2 and key[2]:
+            k = f"{k} ({key[2]})"
         print(f"| {k} | {'x'.join(map(str, g))} | {len(v)} | {sum(v) / 1e6:.1f} | "
               f"{sum(v) / len(v) / 1e3:.2f} | {statistics.median(v) / 1e3:.2f} | "
               f"{min(v) / 1e3:.2f} | {max(v) / 1e3:.2f} |")
@@ -132,6 +139,7 @@ def main(argv=None):
     t = sub.add_parser("trace")
     t.add_argument("csv")
     t.add_argument("--match", default="socfv")
+    t.add_argument("--split-us", type=float, default=None)
     p = sub.add_parser("pmc")
     p.add_argument("--fetch", required=True)
     p.add_argument("--write", required=True)
@@ -143,7 +151,7 @@ def main(argv=None):
                                                     "csrc", "kernels.hip"))
     a = ap.parse_args(argv)
     if a.cmd == "trace":
-        trace(a.csv, a.match)
+        trace(a.csv, a.match, a.split_us)
     else:
         pmc(a.fetch, a.write, a.sq, a.kernel, a.cells, a.updates, a.source)
 
