@@ -56,9 +56,20 @@ __device__ __forceinline__ double block_total(double v, bool mx, double *sh) {
 }
 
 // Sum of a[k * stride] for k < n by the whole block (same value in every thread and block).
+// Eight loads per thread are in flight at once (indices past n read a[0], selected away).
 __device__ __forceinline__ double sum_partials(const double *a, int n, int stride, double *sh) {
   double v = 0.0;
-  for (int k = threadIdx.x; k < n; k += FB) v += a[(long long)k * stride];
+  for (int k0 = 0; k0 < n; k0 += 8 * FB) {
+    double t[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = k0 + j * FB + (int)threadIdx.x;
+      t[j] = a[(long long)(k < n ? k : 0) * stride];
+      t[j] = k < n ? t[j] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v += t[j];
+  }
   return block_total(v, false, sh);
 }
 
@@ -109,17 +120,20 @@ __device__ __forceinline__ PRow prow(uint8_t fl, const Grid &g, int x, int y, in
   return r;
 }
 
-// Sum of v over the open neighbours of a cell
+// Sum of v over the open neighbours of a cell.  Branch-free: a closed neighbour's index is
+// replaced by the cell's own (always in bounds) and its value selected away, so all six loads
+// are in flight together (a load under a branch makes the join wait for every load).
 __device__ __forceinline__ double nb_sum(const double *__restrict__ v, long long c, unsigned nb,
                                          long long sy, long long sz) {
-  double t = 0.0;
-  if (nb & 1u) t += v[c - 1];
-  if (nb & 2u) t += v[c + 1];
-  if (nb & 4u) t += v[c - sy];
-  if (nb & 8u) t += v[c + sy];
-  if (nb & 16u) t += v[c - sz];
-  if (nb & 32u) t += v[c + sz];
-  return t;
+  const double a0 = v[(nb & 1u) ? c - 1 : c];
+  const double a1 = v[(nb & 2u) ? c + 1 : c];
+  const double a2 = v[(nb & 4u) ? c - sy : c];
+  const double a3 = v[(nb & 8u) ? c + sy : c];
+  const double a4 = v[(nb & 16u) ? c - sz : c];
+  const double a5 = v[(nb & 32u) ? c + sz : c];
+  return (((nb & 1u) ? a0 : 0.0) + ((nb & 2u) ? a1 : 0.0)) +
+         (((nb & 4u) ? a2 : 0.0) + ((nb & 8u) ? a3 : 0.0)) +
+         (((nb & 16u) ? a4 : 0.0) + ((nb & 32u) ? a5 : 0.0));
 }
 
 // ---- face classification ---------------------------------------------------------------
@@ -167,11 +181,15 @@ __global__ void __launch_bounds__(FB) k_flow_predict(FlowArgs a) {
     double out = 0.0;
     if (c & FC_OPEN) {
       const double u0 = u[f];
+      double nbv[6];
+#pragma unroll
+      for (int n = 0; n < 6; ++n)      // branch-free gather: closed neighbours read the face
+        nbv[n] = u[((c >> (2 * n)) & 3u) == 1u ? f + off[n] : f];
       double acc = 0.0, diag = 0.0;
 #pragma unroll
       for (int n = 0; n < 6; ++n) {
         const unsigned cls = (c >> (2 * n)) & 3u;
-        if (cls == 1u) acc += u[f + off[n]];
+        acc += cls == 1u ? nbv[n] : 0.0;
         diag += cls == 3u ? 2.0 : (cls != 0u ? 1.0 : 0.0);
       }
       out = u0 + a.dt * (acc - diag * u0);

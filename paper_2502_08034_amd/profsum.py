@@ -29,6 +29,7 @@ def short(name):
     name = name.strip('"')
     if name.startswith("void "):
         name = name[5:]
+    name = name.replace("(anonymous namespace)::", "")
     return name.split("(")[0]
 
 
