@@ -1502,6 +1502,9 @@ int socfv_solve_stokes(socfv_ctx *c, const socfv_flow_params *p, double *ux, dou
     return fail(SOCFV_INVALID_ARG, "max_steps, check_every and cg_max must be >= 1");
   const Grid &g = c->g;
   const long long n = g.n;
+  // the flow kernels decompose face and cell indices in 32 bits
+  if ((long long)(g.nx + 1) * (g.ny + 1) * (g.nz + 1) >= (1ll << 32))
+    return fail(SOCFV_INVALID_ARG, "grid too large for the flow step (2^32 faces)");
   const long long nf[3] = {(long long)(g.nx + 1) * g.ny * g.nz,
                            (long long)g.nx * (g.ny + 1) * g.nz,
                            (long long)g.nx * g.ny * (g.nz + 1)};
@@ -1528,6 +1531,7 @@ int socfv_solve_stokes(socfv_ctx *c, const socfv_flow_params *p, double *ux, dou
     }
     double **cellv[6] = {&a.p, &a.r, &a.z, &a.q, &a.d[0], &a.d[1]};
     for (double **v : cellv) TRY(alloc((void **)v, sizeof(double) * (size_t)n));
+    TRY(alloc((void **)&a.ccode, (size_t)n));
     const long long npart = 5ll * a.nbc + 6ll * a.nbf + 4ll * a.nbc + FS_N;
     double *part = nullptr;
     TRY(alloc((void **)&part, sizeof(double) * (size_t)npart));

@@ -120,6 +120,15 @@ __device__ __forceinline__ PRow prow(uint8_t fl, const Grid &g, int x, int y, in
   return r;
 }
 
+// Cell code byte (built once per call): bits 0..5 the open-neighbour mask, bit 6 the inlet
+// face, bit 7 the outlet face; 0 for fibre cells (a pore cell always has an open face or the
+// inlet: it is face-connected to the inlet).  The CG kernels need nothing else of the cell.
+constexpr unsigned CC_INLET = 64u, CC_OUTLET = 128u;
+__device__ __forceinline__ PRow prow_code(unsigned cc) {
+  return PRow{(double)(__popc(cc & 63u) + 2 * ((cc >> 6) & 1u) + 2 * ((cc >> 7) & 1u)),
+              cc & 63u};
+}
+
 // Sum of v over the open neighbours of a cell.  Branch-free: a closed neighbour's index is
 // replaced by the cell's own (always in bounds) and its value selected away, so all six loads
 // are in flight together (a load under a branch makes the join wait for every load).
@@ -144,9 +153,9 @@ __global__ void __launch_bounds__(FB) k_flow_codes(FlowArgs a) {
   uint16_t *code = a.code[o];
   for (long long f = (long long)blockIdx.x * FB + threadIdx.x; f < d.n;
        f += (long long)gridDim.x * FB) {
-    const int x = (int)(f % d.fx);
-    const long long t = f / d.fx;
-    const int y = (int)(t % d.fy), z = (int)(t / d.fy);
+    const unsigned fu = (unsigned)f, t = fu / (unsigned)d.fx;
+    const int x = (int)(fu - t * (unsigned)d.fx);
+    const int y = (int)(t % (unsigned)d.fy), z = (int)(t / (unsigned)d.fy);
     uint16_t c = 0;
     if (face_open(a.flags, g, o, x, y, z)) {
       c = FC_OPEN;
@@ -162,6 +171,22 @@ __global__ void __launch_bounds__(FB) k_flow_codes(FlowArgs a) {
       }
     }
     code[f] = c;
+  }
+}
+
+__global__ void __launch_bounds__(FB) k_flow_cell_codes(FlowArgs a) {
+  const Grid g = a.g;
+  for (long long c = (long long)blockIdx.x * FB + threadIdx.x; c < g.n;
+       c += (long long)gridDim.x * FB) {
+    const uint8_t fl = a.flags[c];
+    unsigned cc = 0;
+    if (fl & FL_PORE) {
+      const unsigned cu = (unsigned)c, row = cu / (unsigned)g.nx;
+      const int x = (int)(cu - row * (unsigned)g.nx);
+      const int y = (int)(row % (unsigned)g.ny), z = (int)(row / (unsigned)g.ny);
+      cc = prow(fl, g, x, y, z).nb | (x == 0 ? CC_INLET : 0u) | (x == g.nx - 1 ? CC_OUTLET : 0u);
+    }
+    a.ccode[c] = (uint8_t)cc;
   }
 }
 
@@ -213,23 +238,20 @@ __global__ void __launch_bounds__(FB) k_flow_cg_init(FlowArgs a) {
     }
   }
   const long long sy = g.nx, sz = (long long)g.nx * g.ny;
-  const long long fxs = g.nx + 1;
   double rz = 0.0, rr = 0.0;
   for (long long c = (long long)blockIdx.x * FB + threadIdx.x; c < g.n;
        c += (long long)gridDim.x * FB) {
-    const int x = (int)(c % g.nx);
-    const long long t = c / g.nx;
-    const int y = (int)(t % g.ny), z = (int)(t / g.ny);
-    const uint8_t fl = a.flags[c];
+    const unsigned cc = a.ccode[c];
     double rv = 0.0, zv = 0.0;
-    if (fl & FL_PORE) {
-      const long long ix = x + fxs * (y + (long long)g.ny * z);
-      const long long iy = x + (long long)g.nx * (y + (long long)(g.ny + 1) * z);
-      const long long iz = c;
+    if (cc) {
+      // x faces: index c + (y + ny z); y faces: c + nx z
+      const unsigned row = (unsigned)c / (unsigned)g.nx, z = row / (unsigned)g.ny;
+      const long long ix = c + row;
+      const long long iy = c + (long long)g.nx * z;
       const double div = (a.us[0][ix + 1] - a.us[0][ix]) + (a.us[1][iy + g.nx] - a.us[1][iy]) +
-                         (a.us[2][iz + sz] - a.us[2][iz]);
-      const double b = (x == 0 ? 2.0 * a.p_in : 0.0) - div / a.dt;
-      const PRow pr = prow(fl, g, x, y, z);
+                         (a.us[2][c + sz] - a.us[2][c]);
+      const double b = ((cc & CC_INLET) ? 2.0 * a.p_in : 0.0) - div / a.dt;
+      const PRow pr = prow_code(cc);
       const double ap = pr.diag * a.p[c] - nb_sum(a.p, c, pr.nb, sy, sz);
       rv = b - ap;
       zv = rv / pr.diag;
@@ -267,13 +289,10 @@ __global__ void __launch_bounds__(FB) k_flow_cg_a(FlowArgs a, int j) {
   double dq = 0.0;
   for (long long c = (long long)blockIdx.x * FB + threadIdx.x; c < g.n;
        c += (long long)gridDim.x * FB) {
-    const uint8_t fl = a.flags[c];
+    const unsigned cc = a.ccode[c];
     double dv = 0.0, qv = 0.0;
-    if (fl & FL_PORE) {
-      const int x = (int)(c % g.nx);
-      const long long t = c / g.nx;
-      const int y = (int)(t % g.ny), z = (int)(t / g.ny);
-      const PRow pr = prow(fl, g, x, y, z);
+    if (cc) {
+      const PRow pr = prow_code(cc);
       double nbs;
       if (j == 0) {
         dv = zz[c];
@@ -306,12 +325,9 @@ __global__ void __launch_bounds__(FB) k_flow_cg_b(FlowArgs a, int j) {
   double rzn = 0.0, rrn = 0.0;
   for (long long c = (long long)blockIdx.x * FB + threadIdx.x; c < g.n;
        c += (long long)gridDim.x * FB) {
-    const uint8_t fl = a.flags[c];
-    if (!(fl & FL_PORE)) continue;
-    const int x = (int)(c % g.nx);
-    const long long t = c / g.nx;
-    const int y = (int)(t % g.ny), z = (int)(t / g.ny);
-    const PRow pr = prow(fl, g, x, y, z);
+    const unsigned cc = a.ccode[c];
+    if (!cc) continue;
+    const PRow pr = prow_code(cc);
     a.p[c] += alpha * dn[c];
     const double rv = a.r[c] - alpha * a.q[c];
     const double zv = rv / pr.diag;
@@ -344,9 +360,9 @@ __global__ void __launch_bounds__(FB) k_flow_project(FlowArgs a) {
        f += (long long)gridDim.x * FB) {
     double un = 0.0;
     if (code[f] & FC_OPEN) {
-      const int x = (int)(f % d.fx);
-      const long long t = f / d.fx;
-      const int y = (int)(t % d.fy), z = (int)(t / d.fy);
+      const unsigned fu = (unsigned)f, t = fu / (unsigned)d.fx;
+      const int x = (int)(fu - t * (unsigned)d.fx);
+      const int y = (int)(t % (unsigned)d.fy), z = (int)(t / (unsigned)d.fy);
       double gp;
       if (o == 0) {
         const long long c = (long long)x + (long long)g.nx * (y + (long long)g.ny * z);
@@ -382,22 +398,20 @@ __global__ void __launch_bounds__(FB) k_flow_check(FlowArgs a) {
   __shared__ double sh[FB / 64];
   const Grid g = a.g;
   const long long sz = (long long)g.nx * g.ny;
-  const long long fxs = g.nx + 1;
   double dmax = 0.0, qin = 0.0, umax = 0.0, qout = 0.0;
   for (long long c = (long long)blockIdx.x * FB + threadIdx.x; c < g.n;
        c += (long long)gridDim.x * FB) {
-    if (!(a.flags[c] & FL_PORE)) continue;
-    const int x = (int)(c % g.nx);
-    const long long t = c / g.nx;
-    const int y = (int)(t % g.ny), z = (int)(t / g.ny);
-    const long long ix = x + fxs * (y + (long long)g.ny * z);
-    const long long iy = x + (long long)g.nx * (y + (long long)(g.ny + 1) * z);
+    const unsigned cc = a.ccode[c];
+    if (!cc) continue;
+    const unsigned row = (unsigned)c / (unsigned)g.nx, z = row / (unsigned)g.ny;
+    const long long ix = c + row;
+    const long long iy = c + (long long)g.nx * z;
     const double v[6] = {a.u[0][ix], a.u[0][ix + 1], a.u[1][iy], a.u[1][iy + g.nx], a.u[2][c],
                          a.u[2][c + sz]};
     dmax = fmax(dmax, fabs((v[1] - v[0]) + (v[3] - v[2]) + (v[5] - v[4])));
     for (int k = 0; k < 6; ++k) umax = fmax(umax, fabs(v[k]));
-    if (x == 0) qin += v[0];
-    if (x == g.nx - 1) qout += v[1];
+    if (cc & CC_INLET) qin += v[0];
+    if (cc & CC_OUTLET) qout += v[1];
   }
   dmax = block_total(dmax, true, sh);
   qin = block_total(qin, false, sh);
@@ -427,6 +441,7 @@ int flow_face_blocks(const Grid &g) {
 
 void launch_flow_codes(const FlowArgs &a, hipStream_t st) {
   k_flow_codes<<<dim3(a.nbf, 3), FB, 0, st>>>(a);
+  k_flow_cell_codes<<<a.nbc, FB, 0, st>>>(a);
 }
 void launch_flow_predict(const FlowArgs &a, hipStream_t st) {
   k_flow_predict<<<dim3(a.nbf, 3), FB, 0, st>>>(a);

@@ -168,6 +168,7 @@ struct FlowArgs {
   Grid g;
   const uint8_t *flags;
   uint16_t *code[3];
+  uint8_t *ccode;        // per cell: open-neighbour mask | inlet (64) | outlet (128); 0 = fibre
   double *u[3];          // velocity (updated in place by the projection)
   double *us[3];         // predictor output u*
   double *p, *r, *z, *q, *d[2];   // pressure and CG vectors (cells)
