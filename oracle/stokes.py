@@ -26,10 +26,12 @@ discrete problem out on the voxel grid:
   outward normal velocity
 * steady Stokes: L u = G p on open faces, D u = 0 on pore cells (``stokes_steady``, by a sparse
   direct solve of this saddle-point system: the plain definition of the fixed point)
-* one step of the flow simulation with explicit momentum diffusion (``chorin_step``): predictor
-  u* = u + dt L u (Eq. (cp1) without advection), pressure from D G p = D u* / dt (Eq. (cp4)),
-  projection u' = u* - dt G p (Eq. (cp2)); time step from Eq. (time-step-flow) with the
-  advective and force terms absent (``flow_time_step``); stop rule of Eq. (flow-cnvg)
+* one step of the flow simulation (``chorin_step``): with explicit momentum diffusion the
+  predictor u* = u + dt L u (Eq. (cp1) without advection); with implicit diffusion (the
+  algorithm's other branch) (I - dt L) v = u - dt (G p + gbc) with the lagged pressure, then
+  u* = v + dt (G p + gbc); pressure from D G p' = D u* / dt - D gbc (Eq. (cp4)), projection
+  u' = u* - dt (G p' + gbc) (Eq. (cp2)); time step from Eq. (time-step-flow) with the advective
+  and force terms absent (``flow_time_step``); stop rule of Eq. (flow-cnvg)
 
 The momentum advection term is omitted: the flow feeding the state-of-charge solve is taken in
 the Stokes regime, where the paper scales one simulation to all applied pressures.
@@ -201,6 +203,13 @@ class StokesOperators:
             self._lu = spl.splu(self.pressure_matrix().tocsc())
         return self._lu.solve(rhs)
 
+    def helmholtz_solve(self, dt, rhs):
+        """(I - dt L) v = rhs, the implicit momentum-diffusion system (SPD)."""
+        if getattr(self, "_hdt", None) != dt:
+            self._hlu = spl.splu((sp.identity(self.nu) - dt * self.L).tocsc())
+            self._hdt = dt
+        return self._hlu.solve(rhs)
+
 
 def flow_time_step(cfl=0.5, nu=1.0, h=1.0):
     """Eq. (time-step-flow) with C_V of Eq. (time-step-flow-viscous) and the advective and
@@ -222,18 +231,22 @@ def stokes_steady(solid, p_in=1.0, ops=None):
     return ops.unpack(x[:ops.nu], x[ops.nu:])
 
 
-def chorin_step(ops, u, p, dt):
-    """One step of the flow simulation with explicit momentum diffusion on unknown vectors
-    (u over open faces, p over pore cells): predictor, exact pressure Poisson solve,
-    projection.  Returns (u_next, p_next)."""
-    u_star = u + dt * (ops.L @ u)
+def chorin_step(ops, u, p, dt, implicit=False):
+    """One step of the flow simulation on unknown vectors (u over open faces, p over pore
+    cells): predictor (explicit or implicit momentum diffusion), exact pressure Poisson
+    solve, projection.  Returns (u_next, p_next)."""
+    if implicit:
+        gp = ops.G @ p + ops.gbc
+        u_star = ops.helmholtz_solve(dt, u - dt * gp) + dt * gp
+    else:
+        u_star = u + dt * (ops.L @ u)
     # D (u* - dt (G p + gbc)) = 0  <=>  (-D G) p = D gbc - D u* / dt
     p_next = ops.pressure_solve(ops.D @ ops.gbc - (ops.D @ u_star) / dt)
     u_next = u_star - dt * (ops.G @ p_next + ops.gbc)
     return u_next, p_next
 
 
-def flow_sim(solid, p_in=1.0, cfl=0.5, eps=1e-9, max_steps=10**6, ops=None):
+def flow_sim(solid, p_in=1.0, cfl=0.5, eps=1e-9, max_steps=10**6, ops=None, implicit=False):
     """The flow simulation from rest to the stop rule ||u' - u|| < eps ||u'||.  Returns
     (ux, uy, uz, p, steps)."""
     ops = ops or StokesOperators(solid, p_in)
@@ -241,7 +254,7 @@ def flow_sim(solid, p_in=1.0, cfl=0.5, eps=1e-9, max_steps=10**6, ops=None):
     u = np.zeros(ops.nu)
     p = np.zeros(ops.np_)
     for n in range(1, max_steps + 1):
-        un, p = chorin_step(ops, u, p, dt)
+        un, p = chorin_step(ops, u, p, dt, implicit)
         du = np.linalg.norm(un - u)
         u = un
         if du < eps * np.linalg.norm(u):
