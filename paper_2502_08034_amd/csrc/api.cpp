@@ -1576,11 +1576,11 @@ int socfv_solve_stokes(socfv_ctx *c, const socfv_flow_params *p, double *ux, dou
       const double total = c->hres[2];
       if (!std::isfinite(du) || !std::isfinite(un))
         return fail(SOCFV_DIVERGED, "flow steps diverged at step %ld", steps);
-      // launch enough CG iterations for this phase: three times the recent average, at
-      // least 8 (kernels past the stop return at once)
+      // launch enough CG iterations for this phase: twice the recent average plus 4, at
+      // least 8 (kernels past the stop return at once, at about 2 us each)
       const double avg = (total - total_prev) / (double)k;
       total_prev = total;
-      m = std::min(p->cg_max, std::max(8, (int)std::ceil(3.0 * avg) + 8));
+      m = std::min(p->cg_max, std::max(8, (int)std::ceil(2.0 * avg) + 4));
       if (un > 0.0 && du < p->tol * un) {
         status = SOCFV_OK;
         break;
