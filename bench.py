@@ -207,6 +207,7 @@ def logpile_sweep(sv, torch, pes, volts=(-2.0, 0.0, 2.0), s_in=1.7e-7):
 
 
 def stokes_flow(sv, torch, name="fibre256", cfl=0.5, tol=1e-9, max_steps=10**7, scale=None):
+    log(f"flow workload {name}: building the geometry")
     """Upstream flow step on a fibre workload: steady Stokes flow from rest by projection
     steps at the paper's C_CFL = 1/2 and eps_flow = 1e-9, then the SOC solve on that flow."""
     from paper_2502_08034_amd import inputs as I
@@ -219,7 +220,21 @@ def stokes_flow(sv, torch, name="fibre256", cfl=0.5, tol=1e-9, max_steps=10**7, 
     sv.solve_stokes(ctx, cfl=cfl, max_steps=10, check_every=10)       # warm-up
     torch.cuda.synchronize()
     t = time.perf_counter()
-    ux, uy, uz, _, st = sv.solve_stokes(ctx, cfl=cfl, tol=tol, max_steps=max_steps)
+    if n < 50_000_000:
+        ux, uy, uz, _, st = sv.solve_stokes(ctx, cfl=cfl, tol=tol, max_steps=max_steps)
+    else:
+        # large boxes: resumed calls of 2000 steps, each reporting its progress
+        ux, uy, uz, pr, st = sv.solve_stokes(ctx, cfl=cfl, tol=tol, max_steps=2000,
+                                             want_pressure=True)
+        steps, cg = st.steps, st.cg_iterations
+        while st.status == sv.NOT_CONVERGED and steps < max_steps:
+            log(f"flow {nx}x{ny}x{nz}: {steps} steps, change {st.change:.2e}, "
+                f"{time.perf_counter() - t:.1f}s")
+            ux, uy, uz, pr, st = sv.solve_stokes(ctx, cfl=cfl, tol=tol, start=(ux, uy, uz, pr),
+                                                 max_steps=min(2000, max_steps - steps))
+            steps += st.steps
+            cg += st.cg_iterations
+        st.steps, st.cg_iterations = steps, cg
     torch.cuda.synchronize()
     el = time.perf_counter() - t
     log(f"Stokes flow {nx}x{ny}x{nz}: {st.steps} steps, {st.cg_iterations} CG iterations "
@@ -261,6 +276,8 @@ def main():
                     help="upstream flow step: steady Stokes flow on the 256x128x128 fibre "
                          "workload (prints its own JSON line and exits)")
     ap.add_argument("--flow-cfl", type=float, default=0.5)
+    ap.add_argument("--flow-workload", default="fibre256",
+                    help="fibre256 (256x128x128) or slab1024 (1024x512x256)")
     ap.add_argument("--no-flow", action="store_true",
                     help="skip the default run's flow leg (256x128x128 Stokes flow, C_CFL 3.5)")
     ap.add_argument("--flow-max-steps", type=int, default=10**7)
@@ -294,7 +311,8 @@ def main():
         logpile_sweep(sv, torch, pes)
         return
     if args.stokes_flow:
-        print(json.dumps(stokes_flow(sv, torch, cfl=args.flow_cfl, max_steps=args.flow_max_steps,
+        print(json.dumps(stokes_flow(sv, torch, name=args.flow_workload, cfl=args.flow_cfl,
+                                     max_steps=args.flow_max_steps,
                                      scale=parse_scale(args.scale))), flush=True)
         return
     geo, u1, cfg = build_slab(parse_scale(args.scale), "cuda")

@@ -274,11 +274,13 @@ int socfv_solve_soc_upsampled(socfv_ctx *c, const socfv_params *p, double *s_out
  *   cg_theta    pressure CG stop factor (0.1)
  *   max_steps, check_every   step cap; steps between host checks of the stop rule
  *   cg_max      cap on CG iterations per step
+ *   resume      0: start from rest (u = 0, p = 0); 1: start from the velocity in ux, uy, uz
+ *               and, if p_out is given, the pressure in p_out (continuing an earlier call)
  *
  * ux, uy, uz: device, FP64, the staggered layout of socfv_set_velocity, written with the
  * flow (closed faces 0); they also serve as the iteration's velocity, so they hold the last
- * iterate on NOT_CONVERGED or DIVERGED.  p_out (nullable): device, FP64 (nz, ny, nx), the
- * pressure (0 in fibre cells).  Needs a context from socfv_setup_geometry (velocity not
+ * iterate on NOT_CONVERGED or DIVERGED (and the start with resume).  p_out (nullable): device,
+ * FP64 (nz, ny, nx), the pressure (0 in fibre cells; the start pressure with resume).  Needs a context from socfv_setup_geometry (velocity not
  * needed).  Temporary device memory (~72 B per cell) is allocated and freed inside the call.
  * Returns OK, NOT_CONVERGED (outputs written), DIVERGED, INVALID_ARG, HIP_ERROR or OOM.
  */
@@ -286,6 +288,7 @@ typedef struct {
   double p_in, cfl, tol, cg_theta;
   long max_steps;
   int check_every, cg_max;
+  int resume;
 } socfv_flow_params;
 typedef struct {
   long steps, cg_iterations;

@@ -1486,6 +1486,7 @@ void socfv_default_flow_params(socfv_flow_params *p) {
   p->max_steps = 10000000L;
   p->check_every = 50;
   p->cg_max = 256;
+  p->resume = 0;
 }
 
 int socfv_solve_stokes(socfv_ctx *c, const socfv_flow_params *p, double *ux, double *uy,
@@ -1544,10 +1545,14 @@ int socfv_solve_stokes(socfv_ctx *c, const socfv_flow_params *p, double *ux, dou
     a.pdiv = a.pdu + 6ll * a.nbf;
     a.sc = a.pdiv + 4ll * a.nbc;
     TRY(enter(c, hip_stream));
-    // start from rest with zero pressure; zero partials make the first step's CG run to
-    // its cap
-    for (int k = 0; k < 3; ++k) launch_fill_f64(a.u[k], nf[k], 0.0, c->st);
+    // start from rest with zero pressure, or resume from the caller's velocity and pressure;
+    // zero partials make the first step's CG run to its cap
+    if (!p->resume)
+      for (int k = 0; k < 3; ++k) launch_fill_f64(a.u[k], nf[k], 0.0, c->st);
     for (double **v : cellv) launch_fill_f64(*v, n, 0.0, c->st);
+    if (p->resume && p_out)
+      HIPCHK(hipMemcpyAsync(a.p, p_out, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice,
+                            c->st));
     launch_fill_f64(part, npart, 0.0, c->st);
     launch_flow_codes(a, c->st);
     HIPCHK(hipGetLastError());

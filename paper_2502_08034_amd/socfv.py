@@ -47,7 +47,7 @@ class Stats(C.Structure):
 class FlowParams(C.Structure):
     _fields_ = [("p_in", C.c_double), ("cfl", C.c_double), ("tol", C.c_double),
                 ("cg_theta", C.c_double), ("max_steps", C.c_long), ("check_every", C.c_int),
-                ("cg_max", C.c_int)]
+                ("cg_max", C.c_int), ("resume", C.c_int)]
 
 
 class FlowStats(C.Structure):
@@ -281,16 +281,26 @@ def flow_params(**kw) -> FlowParams:
     return fp
 
 
-def solve_stokes(ctx: Context, fp: FlowParams | None = None, want_pressure=False, **kw):
+def solve_stokes(ctx: Context, fp: FlowParams | None = None, want_pressure=False, start=None,
+                 **kw):
     """Steady Stokes flow through the context's pore space (projection steps).  Returns
-    (ux, uy, uz, p or None, stats); float64 CUDA tensors in the staggered layout."""
+    (ux, uy, uz, p or None, stats); float64 CUDA tensors in the staggered layout.  ``start``
+    = (ux, uy, uz, p) of an earlier call resumes from that state (updated in place and
+    returned)."""
     fp = fp if fp is not None else flow_params(**kw)
     nz, ny, nx = ctx.shape
     dev = "cuda"
-    ux = torch.empty((nz, ny, nx + 1), dtype=torch.float64, device=dev)
-    uy = torch.empty((nz, ny + 1, nx), dtype=torch.float64, device=dev)
-    uz = torch.empty((nz + 1, ny, nx), dtype=torch.float64, device=dev)
-    pr = torch.empty((nz, ny, nx), dtype=torch.float64, device=dev) if want_pressure else None
+    if start is not None:
+        ux, uy, uz, pr = start
+        fp.resume = 1
+        _ptr(ux, torch.float64, (nz, ny, nx + 1), "ux")
+        _ptr(uy, torch.float64, (nz, ny + 1, nx), "uy")
+        _ptr(uz, torch.float64, (nz + 1, ny, nx), "uz")
+    else:
+        ux = torch.empty((nz, ny, nx + 1), dtype=torch.float64, device=dev)
+        uy = torch.empty((nz, ny + 1, nx), dtype=torch.float64, device=dev)
+        uz = torch.empty((nz + 1, ny, nx), dtype=torch.float64, device=dev)
+        pr = torch.empty((nz, ny, nx), dtype=torch.float64, device=dev) if want_pressure else None
     st = FlowStats()
     code = _lib.socfv_solve_stokes(ctx.handle, C.byref(fp), _ptr(ux, torch.float64),
                                    _ptr(uy, torch.float64), _ptr(uz, torch.float64),

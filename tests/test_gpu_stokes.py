@@ -139,3 +139,18 @@ def test_flow_error_paths(sv):
     # a step cap short of convergence returns NOT_CONVERGED with the last iterate
     ux, uy, uz, _, st = sv.solve_stokes(ctx, max_steps=20, check_every=20)
     assert st.status == sv.NOT_CONVERGED and st.steps == 20 and st.Q > 0
+
+
+def test_resume_continues_the_iteration(sv):
+    """With the pressure CG held at its cap (a tolerance it cannot reach), 20 steps resumed
+    from the state of 20 earlier steps are bit for bit the 40-step run: the CG vectors are
+    rebuilt every step and the velocity and pressure carry the whole state."""
+    solid = geometry("fibres", 24, 14, 12, seed=47)
+    ctx = sv.setup_geometry(torch.as_tensor(solid, device="cuda"))
+    kw = dict(cfl=2.0, tol=0.0, check_every=10, cg_theta=1e-30, cg_max=60)
+    full = sv.solve_stokes(ctx, want_pressure=True, max_steps=40, **kw)
+    first = sv.solve_stokes(ctx, want_pressure=True, max_steps=20, **kw)
+    resumed = sv.solve_stokes(ctx, start=first[:4], max_steps=20, **kw)
+    assert resumed[4].steps == 20 and resumed[4].status == sv.NOT_CONVERGED
+    for got, want in zip(resumed[:4], full[:4]):
+        assert torch.equal(got, want)
