@@ -292,6 +292,7 @@ def solve_stokes(ctx: Context, fp: FlowParams | None = None, want_pressure=False
     dev = "cuda"
     if start is not None:
         ux, uy, uz, pr = start
+        fp = FlowParams.from_buffer_copy(fp)        # leave the caller's parameters as given
         fp.resume = 1
         _ptr(ux, torch.float64, (nz, ny, nx + 1), "ux")
         _ptr(uy, torch.float64, (nz, ny + 1, nx), "uy")
