@@ -281,6 +281,8 @@ def main():
     ap.add_argument("--no-flow", action="store_true",
                     help="skip the default run's flow leg (256x128x128 Stokes flow, C_CFL 3.5)")
     ap.add_argument("--flow-max-steps", type=int, default=10**7)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="start with the counter-calibration copies (for rocprofv3 --pmc runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--tiles", default=None, help="tile_y,z_chunk for the sweeps")
@@ -297,7 +299,7 @@ def main():
     from paper_2502_08034_amd import socfv as sv
 
     assert torch.cuda.is_available(), "bench needs a GPU"
-    if args.profile_sweeps:
+    if args.profile_sweeps or args.calibrate:
         # counter calibration, first kernels of the process: 4 converting copies of 2^28
         # FP32 values to FP64 (1 GiB read, 2 GiB written each)
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")

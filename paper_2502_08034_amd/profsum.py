@@ -82,23 +82,25 @@ def _calibration(rows, counter):
     return sum(cal) / len(cal)
 
 
-def _kernel_rows(rows, kernel):
+def _kernel_rows(rows, kernel, min_us=None):
     mine = [r for r in rows if short(r[0]).split("<")[0].endswith(kernel)]
+    if min_us is not None:
+        mine = [r for r in mine if r[3] >= min_us * 1e3]
     if not mine:
         raise SystemExit(f"no dispatch of {kernel} in the counter CSV")
     g = max(r[1] for r in mine)
     return [r for r in mine if r[1] == g], g
 
 
-def pmc(fetch, write, sq, kernel, cells, updates, source):
+def pmc(fetch, write, sq, kernel, cells, updates, source, min_us=None):
     fr = _counters(fetch)
     wr = _counters(write)
     f_cal = _calibration(fr, "FETCH_SIZE")
     w_cal = _calibration(wr, "WRITE_SIZE")
     f_fac = CAL_READ / 1024 / f_cal
     w_fac = CAL_WRITE / 1024 / w_cal
-    kf, grid = _kernel_rows(fr, kernel)
-    kw, _ = _kernel_rows(wr, kernel)
+    kf, grid = _kernel_rows(fr, kernel, min_us)
+    kw, _ = _kernel_rows(wr, kernel, min_us)
     f_kib = statistics.mean(c["FETCH_SIZE"] for _, _, c, _ in kf)
     w_kib = statistics.mean(c["WRITE_SIZE"] for _, _, c, _ in kw)
     rd = f_kib * 1024 * f_fac
@@ -107,7 +109,7 @@ def pmc(fetch, write, sq, kernel, cells, updates, source):
     dur = statistics.mean(d for _, _, _, d in kf)
     if source:
         digest = hashlib.sha256(open(source, "rb").read()).hexdigest()
-        print(f"kernels.hip sha256 at measurement: {digest}\n")
+        print(f"{os.path.basename(source)} sha256 at measurement: {digest}\n")
     print("## Calibration (plain copy of known size)\n")
     print("| counter | reads for the copy | expected | factor |")
     print("|---|---|---|---|")
@@ -124,7 +126,7 @@ def pmc(fetch, write, sq, kernel, cells, updates, source):
     print(f"| duration under counters | {dur / 1e3:.1f} us |")
     if sq:
         sr = _counters(sq)
-        ks, _ = _kernel_rows(sr, kernel)
+        ks, _ = _kernel_rows(sr, kernel, min_us)
         names = sorted(ks[0][2])
         for n in names:
             v = statistics.mean(c[n] for _, _, c, _ in ks)
@@ -148,13 +150,15 @@ def main(argv=None):
     p.add_argument("--kernel", required=True)
     p.add_argument("--cells", type=int, required=True)
     p.add_argument("--updates", type=int, default=1)
+    p.add_argument("--min-us", type=float, default=None,
+                   help="average only dispatches lasting at least this long")
     p.add_argument("--source", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                     "csrc", "kernels.hip"))
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         trace(a.csv, a.match, a.split_us)
     else:
-        pmc(a.fetch, a.write, a.sq, a.kernel, a.cells, a.updates, a.source)
+        pmc(a.fetch, a.write, a.sq, a.kernel, a.cells, a.updates, a.source, a.min_us)
 
 
 if __name__ == "__main__":
