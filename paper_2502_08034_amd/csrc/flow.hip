@@ -73,6 +73,14 @@ __device__ __forceinline__ double sum_partials(const double *a, int n, int strid
   return block_total(v, false, sh);
 }
 
+// Workgroups go to the eight XCDs in turn (block b to XCD b % 8), each XCD with its own L2.
+// Renumbering them so that every XCD works one contiguous run of logical blocks keeps a
+// cell's row neighbours (the next block) in the same L2.  A bijection on [0, nb).
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+  const unsigned x = b % 8u, k = b / 8u, q = nb / 8u, r = nb % 8u;
+  return x * q + (x < r ? x : r) + k;
+}
+
 __device__ __forceinline__ bool pore_at(const uint8_t *fl, const Grid &g, int x, int y, int z) {
   return (fl[x + (long long)g.nx * (y + (long long)g.ny * z)] & FL_PORE) != 0;
 }
@@ -151,7 +159,7 @@ __global__ void __launch_bounds__(FB) k_flow_codes(FlowArgs a) {
   const int o = blockIdx.y;
   const FaceDims d = face_dims(g, o);
   uint16_t *code = a.code[o];
-  for (long long f = (long long)blockIdx.x * FB + threadIdx.x; f < d.n;
+  for (long long f = (long long)xcd_block(blockIdx.x, gridDim.x) * FB + threadIdx.x; f < d.n;
        f += (long long)gridDim.x * FB) {
     const unsigned fu = (unsigned)f, t = fu / (unsigned)d.fx;
     const int x = (int)(fu - t * (unsigned)d.fx);
@@ -176,7 +184,7 @@ __global__ void __launch_bounds__(FB) k_flow_codes(FlowArgs a) {
 
 __global__ void __launch_bounds__(FB) k_flow_cell_codes(FlowArgs a) {
   const Grid g = a.g;
-  for (long long c = (long long)blockIdx.x * FB + threadIdx.x; c < g.n;
+  for (long long c = (long long)xcd_block(blockIdx.x, gridDim.x) * FB + threadIdx.x; c < g.n;
        c += (long long)gridDim.x * FB) {
     const uint8_t fl = a.flags[c];
     unsigned cc = 0;
@@ -200,7 +208,7 @@ __global__ void __launch_bounds__(FB) k_flow_predict(FlowArgs a) {
   double *__restrict__ us = a.us[o];
   const long long off[6] = {-1, 1, -(long long)d.fx, (long long)d.fx,
                             -(long long)d.fx * d.fy, (long long)d.fx * d.fy};
-  for (long long f = (long long)blockIdx.x * FB + threadIdx.x; f < d.n;
+  for (long long f = (long long)xcd_block(blockIdx.x, gridDim.x) * FB + threadIdx.x; f < d.n;
        f += (long long)gridDim.x * FB) {
     const unsigned c = code[f];
     double out = 0.0;
@@ -239,7 +247,7 @@ __global__ void __launch_bounds__(FB) k_flow_cg_init(FlowArgs a) {
   }
   const long long sy = g.nx, sz = (long long)g.nx * g.ny;
   double rz = 0.0, rr = 0.0;
-  for (long long c = (long long)blockIdx.x * FB + threadIdx.x; c < g.n;
+  for (long long c = (long long)xcd_block(blockIdx.x, gridDim.x) * FB + threadIdx.x; c < g.n;
        c += (long long)gridDim.x * FB) {
     const unsigned cc = a.ccode[c];
     double rv = 0.0, zv = 0.0;
@@ -287,7 +295,7 @@ __global__ void __launch_bounds__(FB) k_flow_cg_a(FlowArgs a, int j) {
   double *__restrict__ dn = a.d[par];
   const long long sy = g.nx, sz = (long long)g.nx * g.ny;
   double dq = 0.0;
-  for (long long c = (long long)blockIdx.x * FB + threadIdx.x; c < g.n;
+  for (long long c = (long long)xcd_block(blockIdx.x, gridDim.x) * FB + threadIdx.x; c < g.n;
        c += (long long)gridDim.x * FB) {
     const unsigned cc = a.ccode[c];
     double dv = 0.0, qv = 0.0;
@@ -323,7 +331,7 @@ __global__ void __launch_bounds__(FB) k_flow_cg_b(FlowArgs a, int j) {
   const double alpha = rz / dq;
   const double *__restrict__ dn = a.d[par];
   double rzn = 0.0, rrn = 0.0;
-  for (long long c = (long long)blockIdx.x * FB + threadIdx.x; c < g.n;
+  for (long long c = (long long)xcd_block(blockIdx.x, gridDim.x) * FB + threadIdx.x; c < g.n;
        c += (long long)gridDim.x * FB) {
     const unsigned cc = a.ccode[c];
     if (!cc) continue;
@@ -356,7 +364,7 @@ __global__ void __launch_bounds__(FB) k_flow_project(FlowArgs a) {
   double *__restrict__ u = a.u[o];
   const double *__restrict__ p = a.p;
   double du2 = 0.0, u2 = 0.0;
-  for (long long f = (long long)blockIdx.x * FB + threadIdx.x; f < d.n;
+  for (long long f = (long long)xcd_block(blockIdx.x, gridDim.x) * FB + threadIdx.x; f < d.n;
        f += (long long)gridDim.x * FB) {
     double un = 0.0;
     if (code[f] & FC_OPEN) {
@@ -399,7 +407,7 @@ __global__ void __launch_bounds__(FB) k_flow_check(FlowArgs a) {
   const Grid g = a.g;
   const long long sz = (long long)g.nx * g.ny;
   double dmax = 0.0, qin = 0.0, umax = 0.0, qout = 0.0;
-  for (long long c = (long long)blockIdx.x * FB + threadIdx.x; c < g.n;
+  for (long long c = (long long)xcd_block(blockIdx.x, gridDim.x) * FB + threadIdx.x; c < g.n;
        c += (long long)gridDim.x * FB) {
     const unsigned cc = a.ccode[c];
     if (!cc) continue;
