@@ -272,6 +272,25 @@ def residual_norm(pb: Problem, s) -> float:
     return time_scale(pb) * math.sqrt(ss / npore)
 
 
+def correction_iterate(pb: Problem, r0, dt, iters, delta=None):
+    """The inner iteration of iterative refinement on A s = b (the mixed-precision form of
+    the explicit iteration): for a frozen residual r0 = b - A s of some state s,
+    ``iters`` updates delta <- delta + dt (r0 - A delta) from delta = 0 (or ``delta``).
+    A delta is the residual operator with zero boundary values (s_in = s_eq = 0), so
+    fibre and held cells keep delta = 0.  By linearity s + delta_k is the k-th iterate of
+    the explicit iteration started from s.  Returns delta."""
+    z = Problem.__new__(Problem)
+    z.__dict__.update(pb.__dict__)
+    z.s_in, z.s_eq = 0.0, 0.0
+    upd = (pb.solid == 0) & ~((pb.nf > 0) & bool(pb.pinned))
+    r0 = np.where(upd, np.asarray(r0, dtype=np.float64), 0.0)
+    d = np.zeros(pb.solid.shape) if delta is None else np.array(delta, dtype=np.float64)
+    for _ in range(int(iters)):
+        Az, _ = residual(z, d)           # = -A delta on updated cells, 0 elsewhere
+        d = d + dt * (r0 + Az)
+    return d
+
+
 def adjoint_rhs(pb: Problem):
     nx, ny, nz = pb.dims
     g = np.empty(pb.solid.shape, dtype=np.float64)

@@ -388,3 +388,101 @@ def test_adjoint_pinned_mode_flow_gradient(orc, small_fibre):
         Uq.append(orc.outputs(pq, orc.exact_steady(pq))["U"])
     fdq = (Uq[0] - Uq[1]) / (2e-4)
     assert dlnq < 0 and abs(fdq - dlnq) <= 1e-6 * abs(fdq)
+
+
+# ------------------------------------------------------------------------------------
+# Scale of the stop rule (Eq. (convergence-bv-change)): tau = V / Q with the nominal box
+# volume V and the inlet flow Q; RMS over the pore cells
+# ------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,ny,nz,u", [(40, 3, 2, 0.7), (17, 1, 1, 2.5), (64, 5, 4, 0.05)])
+def test_time_scale_is_flow_through_time_of_plug_flow(orc, n, ny, nz, u):
+    # uniform velocity u through an open box: Q = u ny nz, V = n ny nz, so tau = n / u
+    solid, vel = I.plug_flow_case(n, ny, nz, u)
+    pb = orc.Problem(solid, *vel)
+    assert abs(orc.time_scale(pb) - n / u) <= 1e-13 * n / u
+
+
+@pytest.mark.parametrize("n,ny,nz,u,lam", [(40, 3, 2, 0.7, 0.3), (25, 2, 2, 3.0, 0.05)])
+def test_residual_norm_hand_value_in_plug_flow(orc, n, ny, nz, u, lam):
+    # s = s_in = 1 everywhere, s_eq = 0: advection and diffusion cancel in every cell (the
+    # inlet face brings u s_in and nothing diffuses; the outlet removes u s_P), leaving
+    # R_P = -lam in every cell, so rms(R) = lam and res = tau lam = n lam / u
+    solid, vel = I.plug_flow_case(n, ny, nz, u)
+    pb = orc.Problem(solid, *vel, s_in=1.0, s_eq=0.0, lam_field=np.full(solid.shape, lam))
+    s = np.ones(solid.shape)
+    R, _ = orc.residual(pb, s)
+    assert np.abs(R + lam).max() <= 1e-14
+    assert abs(orc.residual_norm(pb, s) - n * lam / u) <= 1e-12 * n * lam / u
+
+
+def test_residual_norm_uses_box_volume_and_pore_count(orc):
+    # a one-cell channel between two fibre layers: V = 3 n (box), Q = u, N = n pore cells,
+    # two fibre faces per cell (lam = 2 Da).  At s = 1: R = -2 Da, res = (3 n / u) 2 Da.
+    # Pore volume in tau (n / u) or the box cell count in the RMS would each fail this.
+    n, u, Da = 30, 1.3, 0.45
+    solid = np.ones((3, 1, n), dtype=np.uint8)
+    solid[1] = 0
+    ux = np.zeros((3, 1, n + 1)); ux[1] = u
+    uy = np.zeros((3, 2, n)); uz = np.zeros((4, 1, n))
+    pb = orc.Problem(solid, ux, uy, uz, s_in=1.0, s_eq=0.0, Da=Da)
+    s = np.where(solid == 0, 1.0, 0.0)
+    assert abs(orc.time_scale(pb) - 3 * n / u) <= 1e-13 * 3 * n / u
+    assert abs(orc.residual_norm(pb, s) - (3 * n / u) * 2 * Da) <= 1e-12 * (3 * n / u) * 2 * Da
+
+
+@pytest.mark.parametrize("pinned", [False, True])
+def test_residual_norm_is_scaled_state_change(orc, small_fibre, pinned):
+    # (tau / dt) ||s' - s||_rms over one explicit update equals tau rms(R), any dt
+    solid, u = small_fibre
+    pb = orc.Problem(solid, *u, s_in=0.0 if pinned else 1.0, s_eq=1.0 if pinned else 0.0,
+                     Da=0.45, pinned=pinned)
+    rng = np.random.default_rng(11)
+    s = np.where(solid == 0, rng.uniform(0, 1, solid.shape), 0.0)
+    if pinned:
+        s = np.where(pb.nf > 0, 1.0, s)
+    pore = solid == 0
+    for dt in (0.4 / orc.max_diag(pb), 1e-3):
+        s1 = orc.iterate(pb, s, dt, 1)
+        rms = math.sqrt(np.mean(((s1 - s)[pore] / dt) ** 2))
+        Q = u[0][:, :, 0][solid[:, :, 0] == 0].sum()
+        ref = solid.size / Q * rms
+        assert abs(orc.residual_norm(pb, s) - ref) <= 1e-9 * ref
+
+
+# ------------------------------------------------------------------------------------
+# Correction (defect) form of the explicit iteration: the FP32 bulk sweeps iterate
+# delta <- delta + dt (r0 - A delta) on a frozen residual r0 = b - A s
+# ------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("pinned", [False, True])
+def test_correction_iteration_continues_the_explicit_iteration(orc, small_fibre, pinned):
+    # linearity: s + delta_k == the k-th explicit iterate from s, for any start s
+    solid, u = small_fibre
+    pb = orc.Problem(solid, *u, s_in=0.0 if pinned else 1.0, s_eq=1.0 if pinned else 0.0,
+                     Da=0.45, pinned=pinned)
+    rng = np.random.default_rng(5)
+    s = np.where(solid == 0, rng.uniform(0, 1, solid.shape), 0.0)
+    if pinned:
+        s = np.where(pb.nf > 0, 1.0, s)
+    dt = 0.4 / orc.max_diag(pb)
+    r0, _ = orc.residual(pb, s)
+    d = orc.correction_iterate(pb, r0, dt, 37)
+    assert np.abs(s + d - orc.iterate(pb, s, dt, 37)).max() <= 1e-13
+    # split into two calls
+    d2 = orc.correction_iterate(pb, r0, dt, 20, delta=orc.correction_iterate(pb, r0, dt, 17))
+    assert np.abs(d2 - d).max() <= 1e-15
+    held = (solid == 1) | ((pb.nf > 0) & pinned)
+    assert np.all(d[held] == 0.0)
+
+
+def test_correction_iteration_fixed_point_is_the_defect(orc, small_fibre):
+    # delta* = A^{-1} r0 = s* - s
+    solid, u = small_fibre
+    pb = orc.Problem(solid, *u, s_in=1.0, s_eq=0.0, Da=0.45)
+    s = pb.initial_state()
+    dt = 0.4 / orc.max_diag(pb)
+    r0, _ = orc.residual(pb, s)
+    d = orc.correction_iterate(pb, r0, dt, 6000)
+    sx = orc.exact_steady(pb)
+    assert np.abs((s + d - sx)[solid == 0]).max() < 1e-8

@@ -208,3 +208,38 @@ def test_implicit_diffusion_steps_reach_the_steady_flow(fibre_geom):
     _, _, _, _, steps_explicit = S.flow_sim(fibre_geom, cfl=2.0, eps=1e-12, ops=ops)
     print(f"implicit {steps} steps, explicit {steps_explicit}")
     assert steps < steps_explicit / 3
+
+
+def paper_flow_dt(cfl, CA, CV, CF):
+    """Eq. (time-step-flow) as printed: dt = 1/2 C_CFL (C_A + C_V + sqrt((C_A + C_V)^2 +
+    4 C_F^2))^-1."""
+    return 0.5 * cfl / (CA + CV + math.sqrt((CA + CV) ** 2 + 4.0 * CF * CF))
+
+
+@pytest.mark.parametrize("cfl,nu,h", [(0.5, 1.0, 1.0), (3.5, 1.0, 1.0), (1.0, 2.0, 0.5),
+                                      (0.25, 0.3, 1.25)])
+def test_flow_time_step_is_the_paper_formula_without_advection_and_force(cfl, nu, h):
+    # C_V from Eq. (time-step-flow-viscous) on a cubic grid: (2 nu)(3 / h^2); no momentum
+    # advection (C_A = 0) and the pressure acting through the projection only (C_F = 0):
+    # dt = C_CFL / (4 C_V) = C_CFL h^2 / (24 nu)
+    CV = 2.0 * nu * (1.0 / h ** 2 + 1.0 / h ** 2 + 1.0 / h ** 2)
+    ref = paper_flow_dt(cfl, 0.0, CV, 0.0)
+    assert abs(ref - cfl * h * h / (24.0 * nu)) <= 1e-15 * ref
+    assert abs(S.flow_time_step(cfl, nu=nu, h=h) - ref) <= 1e-15 * ref
+
+
+@pytest.mark.parametrize("kind", ["open", "fibres"])
+def test_flow_time_step_reaches_the_explicit_stability_limit_at_cfl_4(kind):
+    # explicit momentum diffusion u* = u + dt L u is stable iff dt lambda_max(-L) <= 2; the
+    # viscous operator's spectrum reaches up to 4 per axis (12 in 3D), so C_CFL = 4 sits at
+    # the limit (dt lambda_max just below 2) and the paper's C_CFL = 1/2 far inside it
+    import scipy.sparse.linalg as spl
+    if kind == "open":
+        solid = np.zeros((12, 12, 16), np.uint8)
+    else:
+        solid = I.fibres_nonoverlap(24, 14, 12, 2.5, 0.8, 3).solid
+    L = S.StokesOperators(solid).L
+    assert abs(L - L.T).max() == 0.0
+    lmax = spl.eigsh(-L.tocsc(), k=1, which="LA", return_eigenvectors=False)[0]
+    assert 1.95 < S.flow_time_step(4.0) * lmax <= 2.0
+    assert S.flow_time_step(0.5) * lmax <= 0.25
