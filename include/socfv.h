@@ -83,9 +83,11 @@ typedef struct {
   int precision;      /* SOCFV_FP64, SOCFV_FP32 or SOCFV_FP32_PLAIN */
   double cfl;         /* dt = cfl / max diag; 0 < cfl <= 1 keeps the iteration monotone */
   double tol;         /* stop when res < tol */
-  long max_iter;      /* cap on explicit sweeps (all precisions) */
+  long max_iter;      /* cap on explicit sweeps (all precisions, FP64 polish included;
+                         socfv_batch_solve counts in whole chunks of check_every sweeps) */
   int check_every;    /* sweeps between residual checks (>= 2, even; rounded up to even) */
-  int polish_iters;   /* FP32 mode: FP64 sweeps after the last refresh (0 = check_every) */
+  int polish_iters;   /* FP32 mode: FP64 sweeps after the last refresh once the residual
+                         is below tol (0 = check_every), clipped to what max_iter leaves */
 } socfv_params;
 
 typedef struct {

@@ -411,7 +411,7 @@ struct Solver {
         launch_fill_f32(c->s32[0], n, 0.0f, c->st);
         launch_fill_f32(c->s32[1], n, 0.0f, c->st);
         int cd = 0;
-        const double target = std::fmax(0.5 * p->tol, 1e-4 * res);
+        const double target = std::fmax(p->tol, 1e-4 * res);
         double best = INFINITY;
         int stall = 0;
         while (it < p->max_iter) {
@@ -433,18 +433,14 @@ struct Solver {
         TRY(check(out, res));
       }
       if (res < p->tol) status = SOCFV_OK;
-      // FP64 polish sweeps from the refreshed state
+      // FP64 polish sweeps from the refreshed state, within what max_iter leaves
       long np = p->polish_iters > 0 ? p->polish_iters : chunk_len();
       np += np & 1;
-      if (status == SOCFV_OK || it < p->max_iter) {
+      np = std::min<long>(np, p->max_iter - it);
+      if (status == SOCFV_OK && np > 0) {
         int pc = cur;
-        double *b0 = c->s64[0], *b1 = c->s64[1];
-        (void)b0; (void)b1;
         double pres = res;
-        long save = it;
-        int st2 = run_fp64(pc, pres, np);
-        (void)st2;
-        (void)save;
+        (void)run_fp64(pc, pres, np);
         cur = pc;
         res = pres;
         status = res < p->tol ? SOCFV_OK : SOCFV_NOT_CONVERGED;
@@ -817,7 +813,7 @@ int socfv_solve_soc_adjoint(socfv_ctx *c, const socfv_params *p, double *dU_dkap
       launch_fill_f32(c->s32[0], n, 0.0f, c->st);
       launch_fill_f32(c->s32[1], n, 0.0f, c->st);
       int cd = 0;
-      const double target = std::fmax(0.5 * p->tol, 1e-4 * rel);
+      const double target = std::fmax(p->tol, 1e-4 * rel);
       double best = INFINITY;
       int stall = 0;
       while (S.it < p->max_iter) {
@@ -1179,7 +1175,7 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
       TRY(S[i].refresh(0, 1, nullptr, out.data()));
       res[i] = S[i].res_of(out[0]);
       TRY(S[i].check(out.data(), res[i]));
-      target[i] = std::fmax(0.5 * p[i].tol, 1e-4 * res[i]);
+      target[i] = std::fmax(p[i].tol, 1e-4 * res[i]);
       launch_fill_f32(c->s32[0], c->g.n, 0.0f, bs);
       launch_fill_f32(c->s32[1], c->g.n, 0.0f, bs);
       if (res[i] < p[i].tol) { done[i] = 1; status[i] = SOCFV_OK; }
@@ -1432,7 +1428,7 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
           done[i] = 1;
           changed = true;
         } else {
-          target[i] = std::fmax(0.5 * p[i].tol, 1e-4 * res[i]);
+          target[i] = std::fmax(p[i].tol, 1e-4 * res[i]);
           launch_fill_f32(ctxs[i]->s32[0], ctxs[i]->g.n, 0.0f, bs);
           launch_fill_f32(ctxs[i]->s32[1], ctxs[i]->g.n, 0.0f, bs);
         }
@@ -1443,9 +1439,10 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
       socfv_ctx *c = ctxs[i];
       long np = p[i].polish_iters > 0 ? p[i].polish_iters : S[i].chunk_len();
       np += np & 1;
+      np = std::min<long>(np, p[i].max_iter - S[i].it);
       double pres = res[i];
       int pc = cur[i];
-      TRY(S[i].run_fp64(pc, pres, np));
+      if (status[i] == SOCFV_OK && np > 0) TRY(S[i].run_fp64(pc, pres, np));
       cur[i] = pc;
       res[i] = pres;
       status[i] = pres < p[i].tol ? SOCFV_OK : SOCFV_NOT_CONVERGED;
