@@ -136,7 +136,7 @@ long long partial_need(const Grid &g, const Tiles &t) {
   long long m = (long long)a.x * a.y * a.z;
   m = std::max(m, (long long)b.x * b.y * b.z);
   m = std::max(m, (long long)c.x * c.y * c.z);
-  return NV * m + 64;
+  return std::max(NV * m, (long long)NV2 * march64_blocks(g)) + 64;
 }
 
 int ensure_partial(socfv_ctx *c, long long doubles) {
@@ -149,14 +149,21 @@ int ensure_partial(socfv_ctx *c, long long doubles) {
   return 0;
 }
 
-// reduce nblk x nv partials into host values out[0..nv-1]
-int reduce_to_host(socfv_ctx *c, int nblk, int nv, unsigned maxmask, double *out) {
-  launch_reduce(c->partial, nblk, nv, maxmask, c->dres, c->st);
+// reduce nblk x nv partials (device, at `partial`) into the device slots `dres`, then into
+// host values out[0..nv-1] through the context's pinned mirror
+int reduce_via(socfv_ctx *c, const double *partial, double *dres, int nblk, int nv,
+               unsigned maxmask, double *out) {
+  launch_reduce(partial, nblk, nv, maxmask, dres, c->st);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(c->hres, c->dres, sizeof(double) * nv, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipMemcpyAsync(c->hres, dres, sizeof(double) * nv, hipMemcpyDeviceToHost, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
   for (int k = 0; k < nv; ++k) out[k] = c->hres[k];
   return 0;
+}
+
+// the same with the context's own partials and result slots
+int reduce_to_host(socfv_ctx *c, int nblk, int nv, unsigned maxmask, double *out) {
+  return reduce_via(c, c->partial, c->dres, nblk, nv, maxmask, out);
 }
 
 // join the caller's stream: library work starts after the caller's prior work
@@ -206,6 +213,15 @@ int check_params(const socfv_params *p) {
   if (p->s_in == p->s_eq) return fail(SOCFV_INVALID_ARG, "s_in must differ from s_eq (U undefined)");
   return 0;
 }
+
+// Residual reduction per FP32 correction cycle before the next FP64 refresh.  The FP32
+// update of a correction loses precision once its increments fall far below the correction
+// itself (rounding relative to the correction, not to the increment), which slows the slowly
+// decaying modes; short cycles keep each correction small against its increments, so the
+// cycles take the FP64 iteration's sweep count (measured equal on every parity box and on
+// the 1024 x 512 x 256 slab; a reduction of 1e-4 per cycle took up to 30% more sweeps).  A
+// refresh costs about five FP32 sweeps.
+constexpr double CYCLE_REDUCTION = 0.1;
 
 struct Solver {
   socfv_ctx *c;
@@ -286,14 +302,19 @@ struct Solver {
     for (; j < k; ++j) {
       SweepArgs<T> a = sweep_args<T>(buf[cur], buf[cur ^ 1], dc, j == k - 1 ? c->partial : nullptr);
       a.w = w;
-      launch_sweep<T>(a, t, c->st);
-      cur ^= 1;
-      if (sizeof(T) == 4 && vec4_path(c->g)) {
-        dim3 gv = sweep_grid_v4(c->g, t);
-        nb = (long long)gv.x * gv.y * gv.z;
+      if constexpr (sizeof(T) == 8) {
+        launch_sweep64(a, c->st);
+        nb = march64_blocks(c->g);
       } else {
-        nb = nblk;
+        launch_sweep<T>(a, t, c->st);
+        if (vec4_path(c->g)) {
+          dim3 gv = sweep_grid_v4(c->g, t);
+          nb = (long long)gv.x * gv.y * gv.z;
+        } else {
+          nb = nblk;
+        }
       }
+      cur ^= 1;
     }
     HIPCHK(hipEventRecord(c->t1, c->st));
     HIPCHK(hipGetLastError());
@@ -328,7 +349,7 @@ struct Solver {
     HIPCHK(hipEventRecord(c->t1, c->st));
     HIPCHK(hipGetLastError());
     ++it64;
-    TRY(reduce_to_host(c, (int)nblk, NV, 0u, out));
+    TRY(reduce_to_host(c, march64_blocks(c->g), NV, 0u, out));
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, c->t0, c->t1));
     msref += ms;
@@ -411,7 +432,7 @@ struct Solver {
         launch_fill_f32(c->s32[0], n, 0.0f, c->st);
         launch_fill_f32(c->s32[1], n, 0.0f, c->st);
         int cd = 0;
-        const double target = std::fmax(p->tol, 1e-4 * res);
+        const double target = std::fmax(p->tol, CYCLE_REDUCTION * res);
         double best = INFINITY;
         int stall = 0;
         while (it < p->max_iter) {
@@ -452,14 +473,16 @@ struct Solver {
   }
 };
 
-int eval_outputs(socfv_ctx *c, const socfv_params *p, const double *s, socfv_stats *st) {
+// outputs of state s: per-block partials at `partial` (outputs_blocks x NV2 doubles), the
+// reduced values at `dres` (NV2 doubles); both device memory the caller provides
+int eval_outputs_into(socfv_ctx *c, const socfv_params *p, const double *s, double *partial,
+                      double *dres, socfv_stats *st) {
   const int nb = outputs_blocks(c->g);
-  TRY(ensure_partial(c, (long long)nb * NV2 + 64));
   launch_outputs(c->g, c->flags, faces64(c), c->kappa, s, p->s_in, p->s_eq, p->Da,
-                 p->mode == SOCFV_PINNED, c->partial, nb, c->st);
+                 p->mode == SOCFV_PINNED, partial, nb, c->st);
   HIPCHK(hipGetLastError());
   double o[NV2];
-  TRY(reduce_to_host(c, nb, NV2, 0u, o));
+  TRY(reduce_via(c, partial, dres, nb, NV2, 0u, o));
   st->s_out = o[0] / o[1];
   st->q_out = o[1];
   st->flux_out = o[0];
@@ -472,6 +495,11 @@ int eval_outputs(socfv_ctx *c, const socfv_params *p, const double *s, socfv_sta
   st->tau = tau;
   st->residual = tau * std::sqrt(o[6] / (double)c->npore);
   return 0;
+}
+
+int eval_outputs(socfv_ctx *c, const socfv_params *p, const double *s, socfv_stats *st) {
+  TRY(ensure_partial(c, (long long)outputs_blocks(c->g) * NV2 + 64));
+  return eval_outputs_into(c, p, s, c->partial, c->dres, st);
 }
 
 }  // namespace
@@ -813,7 +841,7 @@ int socfv_solve_soc_adjoint(socfv_ctx *c, const socfv_params *p, double *dU_dkap
       launch_fill_f32(c->s32[0], n, 0.0f, c->st);
       launch_fill_f32(c->s32[1], n, 0.0f, c->st);
       int cd = 0;
-      const double target = std::fmax(p->tol, 1e-4 * rel);
+      const double target = std::fmax(p->tol, CYCLE_REDUCTION * rel);
       double best = INFINITY;
       int stall = 0;
       while (S.it < p->max_iter) {
@@ -836,7 +864,7 @@ int socfv_solve_soc_adjoint(socfv_ctx *c, const socfv_params *p, double *dU_dkap
     if (rel < p->tol) status = SOCFV_OK;
   }
   // gradients
-  const int gb = outputs_blocks(c->g);
+  const int gb = flags_blocks(c->g);
   TRY(ensure_partial(c, (long long)gb * NV + 64));
   launch_gradients(c->g, c->flags, faces64(c), c->s64[c->state_buf], psi[cur], p->s_in, p->s_eq,
                    p->Da, pinned, dU_dkappa, c->partial, gb, c->st);
@@ -1175,7 +1203,7 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
       TRY(S[i].refresh(0, 1, nullptr, out.data()));
       res[i] = S[i].res_of(out[0]);
       TRY(S[i].check(out.data(), res[i]));
-      target[i] = std::fmax(p[i].tol, 1e-4 * res[i]);
+      target[i] = std::fmax(p[i].tol, CYCLE_REDUCTION * res[i]);
       launch_fill_f32(c->s32[0], c->g.n, 0.0f, bs);
       launch_fill_f32(c->s32[1], c->g.n, 0.0f, bs);
       if (res[i] < p[i].tol) { done[i] = 1; status[i] = SOCFV_OK; }
@@ -1428,7 +1456,7 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
           done[i] = 1;
           changed = true;
         } else {
-          target[i] = std::fmax(p[i].tol, 1e-4 * res[i]);
+          target[i] = std::fmax(p[i].tol, CYCLE_REDUCTION * res[i]);
           launch_fill_f32(ctxs[i]->s32[0], ctxs[i]->g.n, 0.0f, bs);
           launch_fill_f32(ctxs[i]->s32[1], ctxs[i]->g.n, 0.0f, bs);
         }

@@ -224,6 +224,10 @@ template <typename T>
 void launch_adjoint(const AdjointArgs<T> &a, const Tiles &t, hipStream_t st);
 void launch_adj_refresh(const AdjRefreshArgs &a, const Tiles &t, hipStream_t st);
 
+// FP64 sweeps (any nx) by the FP64 plane march; partials as for launch_sweep
+void launch_sweep64(const SweepArgs<double> &a, hipStream_t st);
+int march64_blocks(const Grid &g);   // blocks (partial slots) of any FP64 march launch
+
 // outputs of a state: partial per block (NV2 = 8 slots):
 // [sum_out w s, sum_out w, F_in, F_in_adv, reaction, sum_R, sum R^2, -]
 constexpr int NV2 = 8;
@@ -232,7 +236,8 @@ void launch_outputs(const Grid &g, const uint8_t *flags, Faces<double> w, const 
                     double *partial, int nblk, hipStream_t st);
 int outputs_blocks(const Grid &g);
 
-// gradients: dU_dkappa and partial [sum psi Radv, -, -, -]
+// gradients (one thread per cell, flags_blocks(g) blocks): dU_dkappa and partial
+// [sum psi Radv, -, -, -]
 void launch_gradients(const Grid &g, const uint8_t *flags, Faces<double> w, const double *s,
                       const double *psi, double s_in, double s_eq, double Da, int pinned,
                       double *dU_dkappa, double *partial, int nblk, hipStream_t st);

@@ -1232,72 +1232,307 @@ void launch_batch_reduce(const BatchProb *probs, int n, const double *partial, d
 }
 
 // ------------------------------------------------------------------------------------
-// FP64 refresh of the defect correction: t = s64 + delta, r0 = R64(t)
+// FP64 plane march: FP64 sweeps, the FP64 refresh of the defect correction, the outputs
 // ------------------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(1024) k_refresh(RefreshArgs a) {
-  const Grid g = a.g;
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z0 = blockIdx.z * a.zc;
-  const int z1 = min(z0 + a.zc, g.nz);
-  const long long pl = (long long)g.nx * g.ny;
-  double acc[NV] = {0, 0, 0, 0};
-  if (x < g.nx && y < g.ny && z0 < z1) {
-    const int nx = g.nx, ny = g.ny;
-    const bool xl = x > 0, xr = x < nx - 1, yl = y > 0, yr = y < ny - 1;
-    const float *d = a.delta;
-    auto val = [&](long long j) -> double { return a.s64[j] + (d ? (double)d[j] : 0.0); };
-    long long i = x + (long long)nx * (y + (long long)ny * z0);
-    double s_c = val(i);
-    double s_dn = z0 > 0 ? val(i - pl) : 0.0;
-    double wz_c = a.w.wz[i];
-    for (int z = z0; z < z1; ++z, i += pl) {
-      const bool up = z + 1 < g.nz;
-      const double s_up = up ? val(i + pl) : 0.0;
-      const double wz_u = up ? a.w.wz[i + pl] : 0.0;
-      const uint8_t f = a.flags[i];
-      double nv = 0.0;
-      float r0 = 0.0f;
-      if (f & FL_PORE) {
-        Cell<double> q;
-        q.c = s_c; q.zm = s_dn; q.zp = s_up; q.wzm = wz_c; q.wzp = wz_u;
-        q.gzm = (z > 0 && !(f & FL_ZM)) ? 1.0 : 0.0;
-        q.gzp = (up && !(f & FL_ZP)) ? 1.0 : 0.0;
-        q.xm = xl ? val(i - 1) : a.s_in;
-        q.xp = xr ? val(i + 1) : s_c;
-        q.ym = yl ? val(i - nx) : 0.0;
-        q.yp = yr ? val(i + nx) : 0.0;
-        q.wxm = a.w.wx[i];
-        q.wxp = xr ? a.w.wx[i + 1] : a.w.wxo[y + (long long)ny * z];
-        q.wym = a.w.wy[i];
-        q.wyp = yr ? a.w.wy[i + nx] : 0.0;
-        q.gxm = xl ? ((f & FL_XM) ? 0.0 : 1.0) : 2.0;
-        q.gxp = xr ? ((f & FL_XP) ? 0.0 : 1.0) : 0.0;
-        q.gym = (yl && !(f & FL_YM)) ? 1.0 : 0.0;
-        q.gyp = (yr && !(f & FL_YP)) ? 1.0 : 0.0;
-        const int nf = __popc((unsigned)(f & FL_FIBRE));
-        const bool held = a.pinned && nf > 0;
-        const double lam = a.Da * (a.kappa ? (double)a.kappa[i] : 1.0) * (double)nf;
-        double r = held ? 0.0 : residual<double>(q, lam, a.s_eq);
-        nv = held ? a.s_eq : s_c;
-        r0 = (float)r;
-        acc[0] += r * r;
-        acc[2] += r;
-        if (!(nv >= a.lo && nv <= a.hi)) acc[1] += 1.0;
-      }
-      a.s64_new[i] = nv;
-      a.r0[i] = r0;
-      s_dn = s_c;
-      s_c = s_up;
-      wz_c = wz_u;
-    }
+// Blocks of 64 x M64_ROWS lanes, W consecutive x cells per lane (W = 2 for even nx, which
+// makes every row start 16-byte aligned; 1 for odd nx), each block marching a chunk of z.
+// A lane keeps the state of planes j-1 and j in registers and loads plane j+1; rows y-1 and
+// y+1 are loads that the block's neighbouring rows fetch too (cache hits); x neighbours come
+// from the adjacent lanes by DPP shifts, and the wave's edge lanes load theirs.  Small blocks
+// and a short z chunk give many waves per CU to hide the load latency.  The per-cell
+// arithmetic is residual<double>, the same as every other FP64 kernel's.
+constexpr int M64_ROWS = 4;
+
+template <int W>
+struct DW {
+  double v[W];
+};
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+template <int W>
+__device__ __forceinline__ DW<W> ldd(const double *p) {
+  DW<W> r;
+  if constexpr (W == 2) {
+    const d2v t = *(GMEM const d2v *)p;
+    r.v[0] = t.x; r.v[1] = t.y;
+  } else {
+    r.v[0] = *(GMEM const double *)p;
   }
-  block_store<NV>(acc, 0u, a.partial + (long long)NV * (blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)));
+  return r;
 }
 
-void launch_refresh(const RefreshArgs &a, const Tiles &t, hipStream_t st) {
-  k_refresh<<<sweep_grid(a.g, t), dim3(64, t.ty, 1), 0, st>>>(a);
+template <int W>
+__device__ __forceinline__ void std2(double *p, const DW<W> &r) {
+  if constexpr (W == 2) {
+    d2v t;
+    t.x = r.v[0]; t.y = r.v[1];
+    *(GMEM d2v *)p = t;
+  } else {
+    *(GMEM double *)p = r.v[0];
+  }
+}
+
+// s64 + delta at W cells (delta nullable), the state the refresh evaluates
+template <int W, bool DELTA>
+__device__ __forceinline__ DW<W> ldstate(const double *s, const float *d, long long i) {
+  DW<W> r = ldd<W>(s + i);
+  if (DELTA) {
+    const VecW<W> e = ldw<W>(d + i);
+#pragma unroll
+    for (int k = 0; k < W; ++k) r.v[k] += (double)e.v[k];
+  }
+  return r;
+}
+
+// 64-bit lane shifts: lane i receives lane i-1's value (from below) or lane i+1's (from
+// above), as two 32-bit DPP moves; the wave's first / last lane receives 0.
+__device__ __forceinline__ double dlane_from_below(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double dlane_from_above(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+enum { M64_SWEEP = 0, M64_REFRESH = 1, M64_OUTPUTS = 2 };
+
+// Arguments of every FP64 march kernel (the fields an operation does not use are unset).
+struct March64Args {
+  Grid g;
+  const uint8_t *flags;
+  Faces<double> w;
+  const float *kappa;
+  const double *s;      // state (refresh: base state s64)
+  const float *delta;   // refresh: FP32 correction added to s (nullable)
+  double *s_new;        // sweep: s + dt R; refresh: s + delta (held cells s_eq)
+  float *r0;            // refresh: R(s + delta) in FP32
+  double dt, s_in, s_eq, Da;
+  int pinned;
+  double lo, hi;        // bound check on the written state
+  double *partial;      // per block: sweep / refresh NV values, outputs NV2 values
+  int zc;
+};
+
+template <int OP>
+struct M64Acc {
+  static constexpr int K = OP == M64_OUTPUTS ? NV2 : NV;
+};
+
+// OP = M64_SWEEP: s_new = s + dt R(s) (held cells s_eq); with RES the partials
+// [sum R^2, cells out of bounds, sum R, -] over updated cells.
+// OP = M64_REFRESH: t = s + delta; s_new = t (held cells s_eq); r0 = R(t) in FP32 (held 0);
+// partials as for the sweep (RES always).
+// OP = M64_OUTPUTS: partials [sum_out w s, sum_out w, F_in, F_in_adv, reaction, sum R,
+// sum R^2, -] of the state s (as the outputs entry points document).
+template <int W, int OP, bool RES, bool DELTA>
+__global__ void __launch_bounds__(64 * M64_ROWS) k_march64(March64Args a, int gx, int gy,
+                                                             int gz) {
+  constexpr int K = M64Acc<OP>::K;
+  const Grid g = a.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int L = xcd_tile(blockIdx.x, gx * gy * gz);
+  const int bx = L % gx, by = (L / gx) % gy, bz = L / (gx * gy);
+  const int lane = threadIdx.x;
+  const int x = bx * (64 * W) + W * lane;
+  const int y = by * M64_ROWS + threadIdx.y;
+  const int z0 = bz * a.zc;
+  const int z1 = min(z0 + a.zc, nz);
+  const bool act = x < nx && y < ny;
+  const bool yl = y > 0, yr = y < ny - 1;
+  const bool last = x + W >= nx;         // this lane holds the outlet cell
+  const long long pl = (long long)nx * ny;
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  DW<W> sc, sdn, wzc;
+#pragma unroll
+  for (int k = 0; k < W; ++k) sc.v[k] = sdn.v[k] = wzc.v[k] = 0.0;
+  long long i = act ? x + (long long)nx * (y + (long long)ny * z0) : 0;
+  if (act) {
+    sc = ldstate<W, DELTA>(a.s, a.delta, i);
+    if (z0 > 0) sdn = ldstate<W, DELTA>(a.s, a.delta, i - pl);
+    wzc = ldd<W>(a.w.wz + i);
+  }
+  for (int z = z0; z < z1; ++z, i += pl) {
+    const bool up = z + 1 < nz;
+    DW<W> sup, sym, syp, wx, wym, wyp, wzu;
+    VecW<W> kap;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      sup.v[k] = sym.v[k] = syp.v[k] = wx.v[k] = wym.v[k] = wyp.v[k] = wzu.v[k] = 0.0;
+      kap.v[k] = 1.f;
+    }
+    unsigned fl = 0u;
+    if (act) {
+      if (up) {
+        sup = ldstate<W, DELTA>(a.s, a.delta, i + pl);
+        wzu = ldd<W>(a.w.wz + i + pl);
+      }
+      if (yl) sym = ldstate<W, DELTA>(a.s, a.delta, i - nx);
+      if (yr) {
+        syp = ldstate<W, DELTA>(a.s, a.delta, i + nx);
+        wyp = ldd<W>(a.w.wy + i + nx);
+      }
+      wx = ldd<W>(a.w.wx + i);
+      wym = ldd<W>(a.w.wy + i);
+      fl = ldflags<W>(a.flags + i);
+      if (a.kappa) kap = ldw<W>(a.kappa + i);
+    }
+    // x neighbours: the lane below holds x-1, the lane above x+W and the face velocity there
+    double left = dlane_from_below(sc.v[W - 1]);
+    double right = dlane_from_above(sc.v[0]);
+    double wxr = dlane_from_above(wx.v[0]);
+    if (act) {
+      if (x == 0) left = a.s_in;
+      else if (lane == 0) left = ldstate<1, DELTA>(a.s, a.delta, i - 1).v[0];
+      if (last) {
+        wxr = a.w.wxo[y + (long long)ny * z];
+      } else if (lane == 63) {
+        right = ldstate<1, DELTA>(a.s, a.delta, i + W).v[0];
+        wxr = a.w.wx[i + W];
+      }
+    }
+    DW<W> out;
+    VecW<W> rout;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      out.v[k] = 0.0;
+      rout.v[k] = 0.f;
+      const unsigned f = (fl >> (8 * k)) & 0xffu;
+      const int xk = x + k;
+      if (!act || !(f & FL_PORE)) continue;
+      Cell<double> q;
+      q.c = sc.v[k];
+      q.zm = sdn.v[k];
+      q.zp = up ? sup.v[k] : 0.0;
+      q.wzm = wzc.v[k];
+      q.wzp = up ? wzu.v[k] : 0.0;
+      q.gzm = (z > 0 && !(f & FL_ZM)) ? 1.0 : 0.0;
+      q.gzp = (up && !(f & FL_ZP)) ? 1.0 : 0.0;
+      const bool xl = xk > 0, xr = xk < nx - 1;
+      q.xm = k == 0 ? left : sc.v[k - 1];
+      q.xp = xr ? (k == W - 1 ? right : sc.v[k + 1]) : q.c;
+      q.ym = yl ? sym.v[k] : 0.0;
+      q.yp = yr ? syp.v[k] : 0.0;
+      q.wxm = wx.v[k];
+      q.wxp = k == W - 1 ? wxr : wx.v[k + 1];
+      q.wym = wym.v[k];
+      q.wyp = yr ? wyp.v[k] : 0.0;
+      q.gxm = xl ? ((f & FL_XM) ? 0.0 : 1.0) : 2.0;
+      q.gxp = xr ? ((f & FL_XP) ? 0.0 : 1.0) : 0.0;
+      q.gym = (yl && !(f & FL_YM)) ? 1.0 : 0.0;
+      q.gyp = (yr && !(f & FL_YP)) ? 1.0 : 0.0;
+      const int nf = __popc(f & FL_FIBRE);
+      const bool held = a.pinned && nf > 0;
+      const double lam = a.Da * (double)kap.v[k] * (double)nf;
+      if (OP == M64_OUTPUTS) {
+        if (xk == nx - 1) {
+          acc[0] += q.wxp * q.c;
+          acc[1] += q.wxp;
+        }
+        if (xk == 0) {
+          // upwind: inflow brings s_in, outflow through the inlet carries s_P
+          const double adv = fmax(q.wxm, 0.0) * a.s_in + fmin(q.wxm, 0.0) * q.c;
+          acc[2] += adv + 2.0 * (a.s_in - q.c);
+          acc[3] += adv;
+        }
+        if (held) {
+          acc[4] += residual<double>(q, 0.0, a.s_eq);     // absorbed by the electrode cell
+        } else {
+          const double r = residual<double>(q, lam, a.s_eq);
+          acc[4] += lam * (q.c - a.s_eq);
+          acc[5] += r;
+          acc[6] += r * r;
+        }
+      } else {
+        const double r = held ? 0.0 : residual<double>(q, lam, a.s_eq);
+        out.v[k] = held ? a.s_eq : (OP == M64_SWEEP ? q.c + a.dt * r : q.c);
+        rout.v[k] = (float)r;
+        if (RES && !held) {
+          acc[0] += r * r;
+          acc[2] += r;
+        }
+        if (RES && !(out.v[k] >= a.lo && out.v[k] <= a.hi)) acc[1] += 1.0;
+      }
+    }
+    if (OP != M64_OUTPUTS && act) {
+      std2<W>(a.s_new + i, out);
+      if (OP == M64_REFRESH) stw<W>(a.r0 + i, rout);
+    }
+    sdn = sc;
+    sc = sup;
+    wzc = wzu;
+  }
+  if (RES || OP == M64_OUTPUTS) block_store<K>(acc, 0u, a.partial + (long long)K * blockIdx.x);
+}
+
+// z chunk of the march: at most 16 planes, fewer while the grid has under 2048 blocks
+static int march64_zc(const Grid &g) {
+  const int W = (g.nx & 1) ? 1 : 2;
+  const long long gxy = (long long)((g.nx + 64 * W - 1) / (64 * W)) * ((g.ny + M64_ROWS - 1) / M64_ROWS);
+  int zc = 16;
+  while (zc > 2 && gxy * ((g.nz + zc - 1) / zc) < 2048) zc /= 2;
+  return zc;
+}
+
+static dim3 march64_grid(const Grid &g, int zc) {
+  const int W = (g.nx & 1) ? 1 : 2;
+  return dim3((unsigned)((g.nx + 64 * W - 1) / (64 * W)),
+              (unsigned)((g.ny + M64_ROWS - 1) / M64_ROWS), (unsigned)((g.nz + zc - 1) / zc));
+}
+
+int march64_blocks(const Grid &g) {
+  const dim3 d = march64_grid(g, march64_zc(g));
+  return (int)(d.x * d.y * d.z);
+}
+
+template <int OP, bool RES, bool DELTA>
+static void launch_march64(March64Args a, hipStream_t st) {
+  a.zc = march64_zc(a.g);
+  const dim3 d = march64_grid(a.g, a.zc);
+  const unsigned nb = d.x * d.y * d.z;
+  const dim3 block(64, M64_ROWS, 1);
+  if (a.g.nx & 1) k_march64<1, OP, RES, DELTA><<<nb, block, 0, st>>>(a, d.x, d.y, d.z);
+  else k_march64<2, OP, RES, DELTA><<<nb, block, 0, st>>>(a, d.x, d.y, d.z);
+}
+
+void launch_sweep64(const SweepArgs<double> &s, hipStream_t st) {
+  March64Args a{};
+  a.g = s.g; a.flags = s.flags; a.w = s.w; a.kappa = s.kappa;
+  a.s = s.s; a.s_new = s.s_new; a.dt = s.dt; a.s_in = s.s_in; a.s_eq = s.s_eq; a.Da = s.Da;
+  a.pinned = s.pinned; a.lo = s.lo; a.hi = s.hi; a.partial = s.partial;
+  if (s.partial) launch_march64<M64_SWEEP, true, false>(a, st);
+  else launch_march64<M64_SWEEP, false, false>(a, st);
+}
+
+void launch_refresh(const RefreshArgs &r, const Tiles &, hipStream_t st) {
+  March64Args a{};
+  a.g = r.g; a.flags = r.flags; a.w = r.w; a.kappa = r.kappa;
+  a.s = r.s64; a.delta = r.delta; a.s_new = r.s64_new; a.r0 = r.r0;
+  a.s_in = r.s_in; a.s_eq = r.s_eq; a.Da = r.Da; a.pinned = r.pinned; a.lo = r.lo; a.hi = r.hi;
+  a.partial = r.partial;
+  if (r.delta) launch_march64<M64_REFRESH, true, true>(a, st);
+  else launch_march64<M64_REFRESH, true, false>(a, st);
+}
+
+int outputs_blocks(const Grid &g) { return march64_blocks(g); }
+
+void launch_outputs(const Grid &g, const uint8_t *flags, Faces<double> w, const float *kappa,
+                    const double *s, double s_in, double s_eq, double Da, int pinned,
+                    double *partial, int nblk, hipStream_t st) {
+  (void)nblk;
+  March64Args a{};
+  a.g = g; a.flags = flags; a.w = w; a.kappa = kappa; a.s = s;
+  a.s_in = s_in; a.s_eq = s_eq; a.Da = Da; a.pinned = pinned; a.partial = partial;
+  launch_march64<M64_OUTPUTS, false, false>(a, st);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1338,69 +1573,6 @@ __global__ void __launch_bounds__(256) k_maxdiag(Grid g, const uint8_t *__restri
 void launch_maxdiag(const Grid &g, const uint8_t *flags, Faces<double> w, const float *kappa,
                     double Da, int pinned, double *partial, int nblk, hipStream_t st) {
   k_maxdiag<<<nblk, 256, 0, st>>>(g, flags, w, kappa, Da, pinned, partial);
-}
-
-// ------------------------------------------------------------------------------------
-// Outputs of a state: utilisation and the balance of fluxes
-// ------------------------------------------------------------------------------------
-
-int outputs_blocks(const Grid &g) { return (int)((g.n + 255) / 256); }
-
-__global__ void __launch_bounds__(256) k_outputs(Grid g, const uint8_t *__restrict__ flags,
-                                                 Faces<double> w, const float *kappa,
-                                                 const double *__restrict__ s, double s_in,
-                                                 double s_eq, double Da, int pinned,
-                                                 double *partial) {
-  const long long i = blockIdx.x * 256ll + threadIdx.x;
-  double v[NV2] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (i < g.n) {
-    const uint8_t f = flags[i];
-    if (f & FL_PORE) {
-      const int nx = g.nx, ny = g.ny;
-      const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((long long)nx * ny));
-      const long long pl = (long long)nx * ny;
-      const bool up = z + 1 < g.nz;
-      Cell<double> q;
-      q.c = s[i];
-      q.zm = z > 0 ? s[i - pl] : 0.0;
-      q.zp = up ? s[i + pl] : 0.0;
-      q.wzm = w.wz[i];
-      q.wzp = up ? w.wz[i + pl] : 0.0;
-      q.gzm = (z > 0 && !(f & FL_ZM)) ? 1.0 : 0.0;
-      q.gzp = (up && !(f & FL_ZP)) ? 1.0 : 0.0;
-      load_plane<double>(q, s, w, f, g, x, y, z, i, s_in, true);
-      const int nf = __popc((unsigned)(f & FL_FIBRE));
-      const bool held = pinned && nf > 0;
-      if (x == nx - 1) {
-        const double wo = w.wxo[y + (long long)ny * z];
-        v[0] = wo * q.c;
-        v[1] = wo;
-      }
-      if (x == 0) {
-        // upwind: inflow brings s_in, outflow through the inlet carries s_P
-        const double u = w.wx[i];
-        const double adv = fmax(u, 0.0) * s_in + fmin(u, 0.0) * q.c;
-        v[2] = adv + 2.0 * (s_in - q.c);
-        v[3] = adv;
-      }
-      if (held) {
-        v[4] = residual<double>(q, 0.0, s_eq);        // absorbed by the electrode cell
-      } else {
-        const double lam = Da * (kappa ? (double)kappa[i] : 1.0) * nf;
-        const double r = residual<double>(q, lam, s_eq);
-        v[4] = lam * (q.c - s_eq);
-        v[5] = r;
-        v[6] = r * r;
-      }
-    }
-  }
-  block_store<NV2>(v, 0u, partial + (long long)NV2 * blockIdx.x);
-}
-
-void launch_outputs(const Grid &g, const uint8_t *flags, Faces<double> w, const float *kappa,
-                    const double *s, double s_in, double s_eq, double Da, int pinned,
-                    double *partial, int nblk, hipStream_t st) {
-  k_outputs<<<nblk, 256, 0, st>>>(g, flags, w, kappa, s, s_in, s_eq, Da, pinned, partial);
 }
 
 // ------------------------------------------------------------------------------------

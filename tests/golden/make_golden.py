@@ -6,6 +6,7 @@ FP64 sweeps over 4.2M cells on the host), so they are stored here as small JSON 
 scalar outputs plus the state at seeded sample cells.
 
     python tests/golden/make_golden.py fibre256      # finite rate + mass-transport limit
+    python tests/golden/make_golden.py fibre256_mid  # finite rate with U in mid-range
     python tests/golden/make_golden.py adjoint256    # lognormal activity + adjoint
 
 Each file also stores a digest of the generated geometry so a test can tell when the
@@ -79,6 +80,29 @@ def fibre256():
     log("wrote fibre256.json")
 
 
+def fibre256_mid():
+    """The same geometry and flow with a slow surface reaction (Da 0.02 per fibre face, about
+    1/20 of the benchmark's), which puts U near 0.5: at Da 0.45 U saturates (1 - U ~ 3e-4)
+    and an error in U says little about the unconverted fraction."""
+    w = I.workload("fibre256", log=log)
+    solid = w["solid"]
+    ux, uy, uz = w["velocity"][1.0]
+    idx = sample_cells(solid, N_SAMPLE, 2025)
+    res = {"workload": "fibre256, Da 0.02", "shape": list(w["shape"]),
+           "geometry_sha256": digest(solid), "tol": TOL, "check_every": CHECK,
+           "sample_index": idx.tolist()}
+    pb = O.Problem(solid, ux, uy, uz, s_in=1.0, s_eq=0.0, Da=0.02)
+    s, info = solve_ref(pb, "mid")
+    pore = solid == 0
+    res["mid"] = {"s_in": 1.0, "s_eq": 0.0, "Da": 0.02, "pinned": False, "solve": info,
+                  "outputs": O.outputs(pb, s), "s_sample": s.ravel()[idx].tolist(),
+                  "s_min": float(s[pore].min()), "s_max": float(s[pore].max()),
+                  "s_sum": float(s[pore].sum())}
+    with open(os.path.join(HERE, "fibre256_mid.json"), "w") as f:
+        json.dump(res, f)
+    log("wrote fibre256_mid.json")
+
+
 def adjoint256():
     w = I.workload("fibre256", log=log)
     solid = w["solid"]
@@ -109,6 +133,6 @@ def adjoint256():
 
 
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["fibre256", "adjoint256"]
+    which = sys.argv[1:] or ["fibre256", "fibre256_mid", "adjoint256"]
     for name in which:
-        {"fibre256": fibre256, "adjoint256": adjoint256}[name]()
+        {"fibre256": fibre256, "fibre256_mid": fibre256_mid, "adjoint256": adjoint256}[name]()

@@ -1,7 +1,8 @@
 """The benchmark's full-size workloads on the GPU, checked by the FP64 oracle (needs an MI355X).
 
-256 x 128 x 128: against the stored oracle solves (tests/golden/fibre256.json, written by
-tests/golden/make_golden.py from the oracle alone).  1024 x 512 x 256 (the benchmark's slab,
+256 x 128 x 128: against the stored oracle solves (tests/golden/fibre256.json and, for a
+mid-range utilisation, fibre256_mid.json, written by tests/golden/make_golden.py from the
+oracle alone).  1024 x 512 x 256 (the benchmark's slab,
 in the benchmark's launch configuration): by properties the oracle evaluates on the GPU's
 state at any size -- its FP64 residual over every cell, the exact flux balance, the bounds,
 and U recomputed from the state.
@@ -46,6 +47,11 @@ def test_fibre256_against_stored_oracle(sv, orc, mode):
     assert st.status == sv.OK
     Ug = g["outputs"]["U"]
     assert abs(st.U - Ug) <= 1e-6 * abs(Ug)
+    print(f"{mode}: U {st.U:.12f} ref {Ug:.12f}, |dU| / (1 - U) = "
+          f"{abs(st.U - Ug) / (1 - Ug):.2e}")
+    if mode == "finite":
+        # 1 - U ~ 3e-4: the unconverted fraction to 1e-4 relative at residual 1e-8
+        assert abs(st.U - Ug) <= 1e-4 * (1 - Ug)
     # the stored references were converged to 2e-12; at 1e-8 the state is ~1e-9 away
     idx = np.asarray(gold["sample_index"])
     sg = s.view(-1)[torch.as_tensor(idx, device="cuda")].cpu().numpy()
@@ -57,6 +63,33 @@ def test_fibre256_against_stored_oracle(sv, orc, mode):
     pore = solid == 0
     assert sn[pore].min() >= min(g["s_in"], g["s_eq"]) - 1e-9
     assert sn[pore].max() <= max(g["s_in"], g["s_eq"]) + 1e-9
+
+
+def test_fibre256_mid_range_utilisation(sv, orc):
+    """A slow surface reaction (Da 0.02 per fibre face) puts U near 0.5, where an error in U is
+    an error in the unconverted fraction too (at Da 0.45, 1 - U ~ 3e-4, and in the
+    mass-transport limit 1 - U ~ 7e-8, so |dU| / U says little there).  FP32 mode to 1e-8
+    against the stored oracle solve: |dU| <= 1e-6 min(U, 1 - U)."""
+    gold = json.load(open(os.path.join(HERE, "golden", "fibre256_mid.json")))
+    w = I.workload("fibre256", with_velocity=False)
+    solid = w["solid"]
+    assert hashlib.sha256(solid.tobytes()).hexdigest() == gold["geometry_sha256"]
+    u = I.darcy_velocity(solid, 1.0, device="cuda", as_numpy=False)
+    g = gold["mid"]
+    pb = sv.Problem.create(solid, *u)
+    s, st = sv.solve_soc_steady(pb.ctx, sv.params(precision="fp32", tol=1e-8, Da=g["Da"]))
+    assert st.status == sv.OK
+    Ug = g["outputs"]["U"]
+    assert 0.3 < Ug < 0.7
+    err = abs(st.U - Ug)
+    print(f"U {st.U:.12f} ref {Ug:.12f}: |dU| / min(U, 1 - U) = {err / min(Ug, 1 - Ug):.2e}")
+    assert err <= 1e-6 * min(Ug, 1 - Ug)
+    idx = np.asarray(gold["sample_index"])
+    sg = s.view(-1)[torch.as_tensor(idx, device="cuda")].cpu().numpy()
+    assert np.abs(sg - np.asarray(g["s_sample"])).max() <= 1e-5
+    for k in ("flux_in", "flux_out", "reaction"):
+        ok = {"flux_in": "F_in", "flux_out": "F_out", "reaction": "reaction"}[k]
+        assert abs(getattr(st, k) - g["outputs"][ok]) <= 1e-6 * abs(g["outputs"][ok]), k
 
 
 def test_slab1024_in_the_benchmark_configuration(sv, orc):
