@@ -81,6 +81,7 @@ struct socfv_ctx {
   Tiles tiles{4, 8, 32, 1};
   bool tiles_fixed = false;
   int ncu = 1;                   // compute units of the device (for the tile choice)
+  int dev = 0;                   // device holding the context's buffers
   // last forward solution
   bool have_state = false;
   int state_buf = 0;             // s64[state_buf] holds the last steady state
@@ -563,6 +564,17 @@ int socfv_setup_geometry(socfv_ctx **out, int nx, int ny, int nz, const uint8_t 
   socfv_ctx *c = new socfv_ctx();
   c->g = Grid{nx, ny, nz, n};
   c->ncu = ncu;
+  c->dev = dev;
+  {
+    // the allocation-free entry point's scratch: its device address, once per device
+    double *scr = nullptr;
+    const int e = scratch_address(dev, &scr);
+    if (e != 0) {
+      delete c;
+      return fail(SOCFV_HIP_ERROR, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString((hipError_t)e));
+    }
+  }
   c->tiles = auto_tiles(c->g, 16, ncu);
   auto bail = [&](int code) { socfv_destroy(c); return code; };
   if (hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess ||
@@ -742,6 +754,40 @@ int socfv_evaluate(socfv_ctx *c, const socfv_params *p, const double *s, socfv_s
   TRY(enter(c, hip_stream));
   socfv_stats o{};
   TRY(eval_outputs(c, p, s, &o));
+  TRY(leave(c, hip_stream));
+  st->U = o.U; st->s_out = o.s_out; st->flux_in = o.flux_in; st->flux_in_adv = o.flux_in_adv;
+  st->flux_out = o.flux_out; st->reaction = o.reaction; st->sum_R = o.sum_R; st->q_out = o.q_out;
+  st->residual = o.residual; st->tau = o.tau;
+  return SOCFV_OK;
+}
+
+int socfv_evaluate_noalloc(socfv_ctx *c, const socfv_params *p, const double *s,
+                           socfv_stats *st, void *hip_stream) {
+  if (!c || !st) return fail(SOCFV_INVALID_ARG, "NULL argument");
+  TRY(check_params(p));
+  if (!c->have_velocity) return fail(SOCFV_INVALID_ARG, "velocity not set");
+  if (!s) {
+    if (!c->have_state) return fail(SOCFV_INVALID_ARG, "no state in this context");
+    s = c->s64[c->state_buf];
+  }
+  int cur = -1;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != c->dev)
+    return fail(SOCFV_INVALID_ARG, "context lives on device %d; device %d is current", c->dev,
+                cur);
+  double *scr = nullptr;
+  const int e = scratch_address(c->dev, &scr);
+  if (e != 0)
+    return fail(SOCFV_HIP_ERROR, "static scratch of device %d: %s", c->dev,
+                hipGetErrorString((hipError_t)e));
+  const long long nb = outputs_blocks(c->g);
+  if (nb * NV2 + NV2 > SCRATCH_DOUBLES)
+    return fail(SOCFV_INVALID_ARG, "grid too large for the static scratch: %lld blocks x %d "
+                "partials + %d results exceed %lld doubles (at most %lld blocks)", nb, NV2, NV2,
+                SCRATCH_DOUBLES, (SCRATCH_DOUBLES - NV2) / NV2);
+  TRY(enter(c, hip_stream));
+  socfv_stats o{};
+  TRY(eval_outputs_into(c, p, s, scr, scr + nb * NV2, &o));
   TRY(leave(c, hip_stream));
   st->U = o.U; st->s_out = o.s_out; st->flux_in = o.flux_in; st->flux_in_adv = o.flux_in_adv;
   st->flux_out = o.flux_out; st->reaction = o.reaction; st->sum_R = o.sum_R; st->q_out = o.q_out;

@@ -246,6 +246,14 @@ void launch_gradients(const Grid &g, const uint8_t *flags, Faces<double> w, cons
 void launch_reduce(const double *partial, int nblk, int nv, unsigned maxmask, double *out,
                    hipStream_t st);
 
+// Static scratch of the allocation-free entry point: SCRATCH_DOUBLES doubles of device memory
+// per GPU.  scratch_address gives its device address on device dev (which must be current at
+// the first call for that device; the address is looked up once and kept); returns 0 or a
+// hipError_t.
+constexpr long long SCRATCH_DOUBLES = 1ll << 19;      // 4 MiB
+constexpr int SCRATCH_MAX_DEVICES = 64;
+int scratch_address(int dev, double **out);
+
 // helpers
 void launch_fill_f32(float *p, long long n, float v, hipStream_t st);
 void launch_fill_f64(double *p, long long n, double v, hipStream_t st);

@@ -17,6 +17,7 @@
 #include "internal.h"
 
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 namespace socfv {
@@ -1769,6 +1770,35 @@ void launch_gradients(const Grid &g, const uint8_t *flags, Faces<double> w, cons
 template <typename T>
 __global__ void __launch_bounds__(256) k_fill(T *p, long long n, T v) {
   for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += 256ll * gridDim.x) p[i] = v;
+}
+
+// ------------------------------------------------------------------------------------
+// Static scratch of the allocation-free entry point
+// ------------------------------------------------------------------------------------
+
+// Per-block partials and reduced values of socfv_evaluate_noalloc, in device memory that the
+// code object holds (each GPU its own copy, for the life of the process), so that the call
+// needs no allocation.  In host code `scratch` names a host-side stand-in, never the device
+// memory: its device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+int scratch_address(int dev, double **out) {
+  static std::mutex mu;
+  static double *addr[SCRATCH_MAX_DEVICES] = {};
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return (int)e;
+    if (cur != dev) return (int)hipErrorInvalidDevice;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    addr[dev] = static_cast<double *>(p);
+  }
+  *out = addr[dev];
+  return 0;
 }
 
 static unsigned fill_blocks(long long n) {

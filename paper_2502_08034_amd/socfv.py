@@ -81,6 +81,7 @@ def _load():
         "socfv_solve_soc_steady": (i, [P, C.POINTER(Params), P, P, C.POINTER(Stats), P]),
         "socfv_compute_umt": (i, [P, C.POINTER(Params), C.POINTER(d), P, C.POINTER(Stats), P]),
         "socfv_evaluate": (i, [P, C.POINTER(Params), P, C.POINTER(Stats), P]),
+        "socfv_evaluate_noalloc": (i, [P, C.POINTER(Params), P, C.POINTER(Stats), P]),
         "socfv_solve_soc_adjoint": (i, [P, C.POINTER(Params), P, C.POINTER(d), P,
                                         C.POINTER(Stats), P]),
         "socfv_batch_solve": (i, [i, PP, C.POINTER(Params), PP, C.POINTER(Stats), P]),
@@ -231,6 +232,15 @@ def evaluate(ctx: Context, p: Params, s=None) -> Stats:
     st = Stats()
     _check(_lib.socfv_evaluate(ctx.handle, C.byref(p), _ptr(s, torch.float64, ctx.shape, "s"),
                                C.byref(st), _stream()))
+    return st
+
+
+def evaluate_noalloc(ctx: Context, p: Params, s=None) -> Stats:
+    """socfv_evaluate through the allocation-free entry point (static device scratch)."""
+    st = Stats()
+    _check(_lib.socfv_evaluate_noalloc(ctx.handle, C.byref(p),
+                                       _ptr(s, torch.float64, ctx.shape, "s"), C.byref(st),
+                                       _stream()))
     return st
 
 
