@@ -145,7 +145,9 @@ int socfv_set_velocity(socfv_ctx *c, const double *ux, const double *uy, const d
 int socfv_set_activity(socfv_ctx *c, const float *kappa, void *hip_stream);
 
 /*
- * Steady state by the explicit iteration.  s_init (device FP64 (nz,ny,nx), nullable):
+ * Steady state by the explicit iteration.  In FP32 mode the loop's stop rule and refresh
+ * decisions are taken on the device after every check_every sweeps; the host enqueues chunks
+ * ahead and reads the state between groups of them.  s_init (device FP64 (nz,ny,nx), nullable):
  * start state (default s_in on pore cells); held cells always start at s_eq.
  * s_out (device FP64 (nz,ny,nx), nullable): steady state (fibre cells 0).  The state is
  * also kept in the context for socfv_solve_soc_adjoint.  st (host, nullable): stats,
@@ -212,10 +214,13 @@ int socfv_solve_soc_adjoint(socfv_ctx *c, const socfv_params *p, double *dU_dkap
  * Many problems (contexts with geometry and velocity set; uneven sizes allowed) solved
  * together.  With every p[i].precision == SOCFV_FP32, each FP32 sweep is one launch over
  * a tile work list spanning all unfinished problems (persistent blocks, contiguous tile
- * runs per XCD), chunks of check_every sweeps are captured once as a hipGraph and
- * replayed, and each problem keeps its own dt, tau, FP64 refreshes and stopping rule
- * (its own p[i]); the block shape is chosen by timing candidates on the batch.  Other
- * precisions solve the problems one after another.  p, st: host arrays of n entries;
+ * runs per XCD), and each problem keeps its own dt, tau, FP64 refreshes and stopping rule
+ * (its own p[i]), all decided on the device: one chunk of check_every sweeps (rounded up to
+ * a multiple of 4) with the work lists, the per-problem residuals and decisions and the
+ * refreshes is captured once as a hipGraph and replayed, the host reading the problems'
+ * states every few chunks to re-tile the remaining ones; the single-sweep block shape is
+ * chosen by timing candidates on the batch.  Other precisions solve the problems one after
+ * another.  p, st: host arrays of n entries;
  * s_out: host array of n device pointers (nullable, entries nullable).  Returns the worst
  * status (OK < NOT_CONVERGED) or the first error.
  */
@@ -324,11 +329,14 @@ int socfv_solve_stokes(socfv_ctx *c, const socfv_flow_params *p, double *ux, dou
 
 /*
  * Launch shapes.  Single sweeps work on (64 x tile_y) lanes marching z_chunk cells along z;
- * with two_sweeps set (the default), FP32 sweeps on grids with even nx run two sweeps per
- * launch on 64 x 16 lanes marching z_chunk2 cells.  socfv_set_tiles overrides them for a
- * context (0 = keep, two_sweeps < 0 = keep); socfv_autotune times candidate shapes on this
- * context's problem (`sweeps` sweeps each) and keeps the fastest; best[3] (host, nullable)
- * receives tile_y, z_chunk, z_chunk2.
+ * with two_sweeps set (the default), FP32 sweeps run two sweeps per launch on blocks of 1024
+ * lanes marching z_chunk2 cells: rows of 64 lanes (16 rows) or, where that wastes fewer lanes
+ * on the box, rows of 32 lanes (32 rows), two cells per lane for even nx and one for odd.
+ * socfv_set_tiles overrides them for a context (0 = keep; two_sweeps: -1 keep, 0 off, 1 on
+ * with the row width chosen for the box, 2 on with 64-lane rows, 3 on with 32-lane rows; a
+ * new row width re-picks z_chunk2 unless given); socfv_autotune times candidate shapes on
+ * this context's problem (`sweeps` sweeps each) and keeps the fastest; best[3] (host,
+ * nullable) receives tile_y, z_chunk, z_chunk2.
  */
 int socfv_set_tiles(socfv_ctx *c, int tile_y, int z_chunk, int z_chunk2, int two_sweeps);
 int socfv_autotune(socfv_ctx *c, int sweeps, int best[3], void *hip_stream);

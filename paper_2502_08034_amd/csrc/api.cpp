@@ -75,6 +75,9 @@ struct socfv_ctx {
   long long partial_cap = 0;     // doubles
   double *dres = nullptr;        // device result slots
   double *hres = nullptr;        // pinned host mirror
+  SolveCtl *dctl = nullptr;      // device-side control state of the FP32 solve
+  SolveCtl *hctl = nullptr;      // pinned host mirror
+  hipEvent_t evp[4 * 8] = {};    // timing events of a group of chunks
   long npore = 0, nreact = 0, ninlet = 0, noutlet = 0;
   bool have_velocity = false;
   double Q_in = 0, div_max = 0, u_max = 0;
@@ -94,13 +97,13 @@ Faces<float> faces32(const socfv_ctx *c) { return {c->w32[0], c->w32[1], c->w32[
 Faces<double> faces64(const socfv_ctx *c) { return {c->w64[0], c->w64[1], c->w64[2], c->w64[3]}; }
 
 // Two-sweep launches run one block per CU (its LDS and registers fill a CU), each block
-// marching one (62 W) x 14 output tile (W cells per lane) through a z chunk plus two extra
-// planes.  The chunk
+// marching one tile of shape (W, rx) through a z chunk plus two extra planes.  The chunk
 // count is chosen to minimise (rounds of blocks over the CUs) x (planes per block), with
 // chunks of at least 8 planes unless nz is smaller.
-int pick_zc2(const Grid &g, int ncu) {
-  const int ox = 62 * two_w(g);
-  const long long t2 = (long long)((g.nx + ox - 1) / ox) * ((g.ny + 13) / 14);
+int pick_zc2(const Grid &g, int ncu, int rx) {
+  int gx, gy;
+  tile2_xy(g.nx, g.ny, two_w(g), rx, gx, gy);
+  const long long t2 = (long long)gx * gy;
   if (ncu < 1) ncu = 1;
   long long best = -1;
   int zbest = g.nz;
@@ -123,7 +126,10 @@ Tiles auto_tiles(const Grid &g, int ty, int ncu) {
   if (zc < 1) zc = 1;
   if (zc > 32) zc = 32;
   if (zc > g.nz) zc = g.nz;
-  return Tiles{ty, (int)zc, pick_zc2(g, ncu), 1};
+  const int rx = pick_rx(g.nx, g.ny, two_w(g));
+  Tiles t{ty, (int)zc, pick_zc2(g, ncu, rx), 1};
+  t.rx = rx;
+  return t;
 }
 
 long long sweep_blocks(const Grid &g, const Tiles &t) {
@@ -189,6 +195,10 @@ int ensure_state(socfv_ctx *c) {
     if (!c->s32[k]) HIPCHK(hipMalloc(&c->s32[k], sizeof(float) * n));
   }
   if (!c->r0) HIPCHK(hipMalloc(&c->r0, sizeof(float) * n));
+  if (!c->dctl) HIPCHK(hipMalloc(&c->dctl, sizeof(SolveCtl)));
+  if (!c->hctl) HIPCHK(hipHostMalloc(&c->hctl, sizeof(SolveCtl), hipHostMallocDefault));
+  for (hipEvent_t &e : c->evp)
+    if (!e) HIPCHK(hipEventCreate(&e));
   return ensure_partial(c, partial_need(c->g, c->tiles));
 }
 
@@ -280,13 +290,14 @@ struct Solver {
     return a;
   }
 
-  // k sweeps ping-ponging buf[cur] -> buf[cur^1]; partials from the last one.
+  // Enqueue k sweeps ping-ponging buf[cur] -> buf[cur^1], partials from the last one (gate:
+  // nullable device flag, see SweepArgs); returns the partials' block count.
   template <typename T>
-  int chunk(T *buf0, T *buf1, int &cur, int k, bool dc, Faces<T> w, double out[NV]) {
+  long long launch_sweeps(T *buf0, T *buf1, int &cur, int k, bool dc, Faces<T> w,
+                          const int *gate) {
     T *buf[2] = {buf0, buf1};
     const bool two = sizeof(T) == 4 && two_path(c->g) && t.two;
     long long nb = nblk;
-    HIPCHK(hipEventRecord(c->t0, c->st));
     int j = 0;
     if (two) {
       // two sweeps per launch; an odd remainder ends with one single sweep
@@ -294,6 +305,7 @@ struct Solver {
         const bool lastl = j + 2 >= k;
         SweepArgs<T> a = sweep_args<T>(buf[cur], buf[cur ^ 1], dc, lastl ? c->partial : nullptr);
         a.w = w;
+        a.gate = gate;
         launch_sweep2(reinterpret_cast<const SweepArgs<float> &>(a), t, c->st);
         cur ^= 1;
       }
@@ -303,6 +315,7 @@ struct Solver {
     for (; j < k; ++j) {
       SweepArgs<T> a = sweep_args<T>(buf[cur], buf[cur ^ 1], dc, j == k - 1 ? c->partial : nullptr);
       a.w = w;
+      a.gate = gate;
       if constexpr (sizeof(T) == 8) {
         launch_sweep64(a, c->st);
         nb = march64_blocks(c->g);
@@ -317,6 +330,14 @@ struct Solver {
       }
       cur ^= 1;
     }
+    return nb;
+  }
+
+  // k sweeps (as launch_sweeps), timed, then their partials reduced on the host
+  template <typename T>
+  int chunk(T *buf0, T *buf1, int &cur, int k, bool dc, Faces<T> w, double out[NV]) {
+    HIPCHK(hipEventRecord(c->t0, c->st));
+    const long long nb = launch_sweeps<T>(buf0, buf1, cur, k, dc, w, nullptr);
     HIPCHK(hipEventRecord(c->t1, c->st));
     HIPCHK(hipGetLastError());
     TRY(reduce_to_host(c, (int)nb, NV, 0u, out));
@@ -389,6 +410,108 @@ struct Solver {
     return status;
   }
 
+  // FP32 correction cycles with the loop's decisions on the device (SolveCtl): per chunk
+  // of K sweeps, the corrections are zeroed if a cycle starts (k_fill2_gated), the sweeps run
+  // while the state is CTL_RUN, k_ctl_chunk takes the correction residual and the cycle's end
+  // test, the refresh runs if it asked for one, and k_ctl_refresh applies the stop rule and
+  // starts the next cycle.  The host enqueues groups of chunks and reads the state once per
+  // group; launches after the stop return at once.  From s64[cur] with FP64 residual res.
+  int run_dc_device(int &cur, double &res) {
+    constexpr int G = 8;                 // most chunks per group (4 events each)
+    const int K = chunk_len();
+    const long long n = c->g.n;
+    SolveCtl &h = *c->hctl;
+    h = SolveCtl{};
+    h.state = CTL_RUN;
+    h.fill = 1;
+    h.cur = cur;
+    h.max_iter = p->max_iter - it;
+    h.tol = p->tol;
+    h.tau = tau;
+    h.npore = (double)c->npore;
+    h.reduction = CYCLE_REDUCTION;
+    h.target = std::fmax(p->tol, CYCLE_REDUCTION * res);
+    h.best = INFINITY;
+    h.res = res;
+    h.ri = INFINITY;
+    const long long budget = h.max_iter;
+    HIPCHK(hipMemcpyAsync(c->dctl, c->hctl, sizeof(SolveCtl), hipMemcpyHostToDevice, c->st));
+    const int nbr = march64_blocks(c->g);
+    long long known = 0;                 // sweeps done at the last read of the state
+    long long it_prev = -1;              // sweeps and correction residual at the read before
+    double ri_prev = 0;
+    int ng = 2;                          // chunks in the next group
+    for (;;) {
+      int ks[G];
+      int nch = 0;
+      long long enq = known;
+      for (; nch < ng && enq < budget; ++nch) {
+        const int k = (int)std::min<long long>(K, budget - enq);
+        launch_fill_gated(c->s32[0], c->s32[1], n, c->dctl, c->st);
+        HIPCHK(hipEventRecord(c->evp[4 * nch], c->st));
+        int cd = 0;
+        const long long nb = launch_sweeps<float>(c->s32[0], c->s32[1], cd, k, true, faces32(c),
+                                                  &c->dctl->state);
+        HIPCHK(hipEventRecord(c->evp[4 * nch + 1], c->st));
+        launch_ctl_chunk(c->dctl, c->partial, (int)nb, k, c->st);
+        RefreshArgs a;
+        a.g = c->g; a.flags = c->flags; a.w = faces64(c); a.kappa = c->kappa;
+        a.s64 = nullptr; a.delta = c->s32[cd]; a.s64_new = nullptr; a.r0 = c->r0;
+        a.s_in = p->s_in; a.s_eq = p->s_eq; a.Da = p->Da; a.pinned = pinned;
+        a.lo = lo; a.hi = hi; a.partial = c->partial; a.zc = t.zc;
+        HIPCHK(hipEventRecord(c->evp[4 * nch + 2], c->st));
+        launch_refresh_gated(a, c->s64[0], c->s64[1], c->dctl, c->st);
+        HIPCHK(hipEventRecord(c->evp[4 * nch + 3], c->st));
+        launch_ctl_refresh(c->dctl, c->partial, nbr, c->st);
+        ks[nch] = k;
+        enq += k;
+      }
+      HIPCHK(hipGetLastError());
+      const int cyc0 = h.cycles;
+      HIPCHK(hipMemcpyAsync(c->hctl, c->dctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(hipStreamSynchronize(c->st));
+      // GPU time of the chunks whose sweeps ran (the first ones of the group), and of the
+      // refreshes that ran (the longest refresh launches; the others returned at once)
+      long long ran = h.it - known;
+      float refresh_ms[G];
+      for (int g = 0; g < nch; ++g) {
+        float ms = 0;
+        if (ran >= ks[g]) {
+          HIPCHK(hipEventElapsedTime(&ms, c->evp[4 * g], c->evp[4 * g + 1]));
+          ms32 += ms;
+          ran -= ks[g];
+        }
+        HIPCHK(hipEventElapsedTime(&refresh_ms[g], c->evp[4 * g + 2], c->evp[4 * g + 3]));
+      }
+      std::sort(refresh_ms, refresh_ms + nch);
+      for (int g = nch - 1; g >= 0 && g >= nch - (h.cycles - cyc0); --g) msref += refresh_ms[g];
+      known = h.it;
+      if (h.state == CTL_DIVERGED || h.state == CTL_DONE || h.state == CTL_STOP || nch == 0) break;
+      // next group: about half the chunks the residual's decay rate since the last read
+      // still needs to reach tol (the correction residual continues the explicit
+      // iteration's residual across refreshes), between 1 and G, so that few launches are
+      // enqueued past the stop
+      ng = G;
+      if (it_prev >= 0 && h.it > it_prev && ri_prev > 0 && h.ri > 0 && h.ri < ri_prev) {
+        const double per = std::log(h.ri / ri_prev) / (double)(h.it - it_prev);
+        const double left = std::log(p->tol / h.ri) / per;            // sweeps to tol
+        ng = (int)std::max(1.0, std::min((double)G, std::floor(left / K / 2.0)));
+      }
+      it_prev = h.it;
+      ri_prev = h.ri;
+    }
+    it += known;
+    it32 += known;
+    cycles += h.cycles;
+    it64 += h.cycles;
+    cur = h.cur;
+    res = h.res;
+    if (h.state == CTL_DIVERGED)
+      return fail(SOCFV_DIVERGED, "correction sweeps or refresh diverged at sweep %ld "
+                  "(residual %g)", it, std::isfinite(h.ri) ? h.res : h.ri);
+    return 0;
+  }
+
   int solve(const double *s_init, double *res_final, int *state_buf) {
     TRY(setup());
     const long long n = c->g.n;
@@ -428,32 +551,7 @@ struct Solver {
       cur = 1;
       res = res_of(out[0]);
       TRY(check(out, res));
-      const int K = chunk_len();
-      while (res >= p->tol && it < p->max_iter) {
-        launch_fill_f32(c->s32[0], n, 0.0f, c->st);
-        launch_fill_f32(c->s32[1], n, 0.0f, c->st);
-        int cd = 0;
-        const double target = std::fmax(p->tol, CYCLE_REDUCTION * res);
-        double best = INFINITY;
-        int stall = 0;
-        while (it < p->max_iter) {
-          long k = std::min<long>(K, p->max_iter - it);
-          TRY(chunk<float>(c->s32[0], c->s32[1], cd, (int)k, true, faces32(c), out));
-          it += k;
-          it32 += k;
-          const double ri = res_of(out[0]);
-          if (!std::isfinite(ri) || out[1] > 0)
-            return fail(SOCFV_DIVERGED, "correction sweeps diverged at sweep %ld", it);
-          if (ri < target) break;
-          if (ri < 0.999 * best) { best = ri; stall = 0; }
-          else if (++stall >= 8) break;
-        }
-        TRY(refresh(cur, cur ^ 1, c->s32[cd], out));
-        cur ^= 1;
-        ++cycles;
-        res = res_of(out[0]);
-        TRY(check(out, res));
-      }
+      if (res >= p->tol && it < p->max_iter) TRY(run_dc_device(cur, res));
       if (res < p->tol) status = SOCFV_OK;
       // FP64 polish sweeps from the refreshed state, within what max_iter leaves
       long np = p->polish_iters > 0 ? p->polish_iters : chunk_len();
@@ -542,6 +640,10 @@ void socfv_destroy(socfv_ctx *c) {
   hfree(c->partial);
   hfree(c->dres);
   if (c->hres) (void)hipHostFree(c->hres);
+  hfree(c->dctl);
+  if (c->hctl) (void)hipHostFree(c->hctl);
+  for (hipEvent_t e : c->evp)
+    if (e) (void)hipEventDestroy(e);
   if (c->ev) (void)hipEventDestroy(c->ev);
   if (c->t0) (void)hipEventDestroy(c->t0);
   if (c->t1) (void)hipEventDestroy(c->t1);
@@ -1083,7 +1185,16 @@ int socfv_set_tiles(socfv_ctx *c, int tile_y, int z_chunk, int z_chunk2, int two
       return fail(SOCFV_INVALID_ARG, "z_chunk2 must be in [1, 4096]");
     c->tiles.zc2 = z_chunk2;
   }
-  if (two_sweeps >= 0) c->tiles.two = two_sweeps ? 1 : 0;
+  if (two_sweeps > 3) return fail(SOCFV_INVALID_ARG, "two_sweeps must be -1, 0, 1, 2 or 3");
+  if (two_sweeps >= 0) {
+    c->tiles.two = two_sweeps ? 1 : 0;
+    const int rx = two_sweeps == 2 ? 64 : two_sweeps == 3 ? 32
+                                                           : pick_rx(c->g.nx, c->g.ny, two_w(c->g));
+    if (two_sweeps > 0 && rx != c->tiles.rx) {
+      c->tiles.rx = rx;
+      if (z_chunk2 == 0) c->tiles.zc2 = pick_zc2(c->g, c->ncu, rx);
+    }
+  }
   c->tiles_fixed = true;
   return ensure_partial(c, partial_need(c->g, c->tiles));
 }
@@ -1113,6 +1224,7 @@ int socfv_autotune(socfv_ctx *c, int sweeps, int best[3], void *hip_stream) {
     for (int zc : zcs) {
       if (zc > c->g.nz) continue;
       Tiles t{ty, zc, c->tiles.zc2, c->tiles.two};
+      t.rx = c->tiles.rx;
       S.t = t;
       S.nblk = sweep_blocks(c->g, t);
       int cur = 0;
@@ -1144,7 +1256,7 @@ int socfv_autotune(socfv_ctx *c, int sweeps, int best[3], void *hip_stream) {
   float best2 = 1e30f;
   int best_zc2 = c->tiles.zc2;
   if (two_path(c->g)) {
-    const int zc2s[] = {pick_zc2(c->g, c->ncu), 8, 16, 32, 64, 128};
+    const int zc2s[] = {pick_zc2(c->g, c->ncu, c->tiles.rx), 8, 16, 32, 64, 128};
     for (int zc2 : zc2s) {
       if (zc2 > c->g.nz && zc2 != 8) continue;
       Tiles t = best_t;
@@ -1221,6 +1333,7 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
   BatchProb *d_probs = nullptr;
   int *d_tiles = nullptr, *d_work = nullptr, *d_nwork = nullptr, *h_work = nullptr;
   double *d_part = nullptr, *d_out = nullptr, *h_out = nullptr;
+  SolveCtl *d_ctl = nullptr, *h_ctl = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   auto cleanup = [&]() {
@@ -1228,8 +1341,10 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
     if (graph) (void)hipGraphDestroy(graph);
     (void)hipStreamSynchronize(bs);
     hfree(d_probs); hfree(d_tiles); hfree(d_work); hfree(d_nwork); hfree(d_part); hfree(d_out);
+    hfree(d_ctl);
     if (h_work) (void)hipHostFree(h_work);
     if (h_out) (void)hipHostFree(h_out);
+    if (h_ctl) (void)hipHostFree(h_ctl);
     for (int i = 0; i < n; ++i) ctxs[i]->st = saved[i];
     (void)hipStreamDestroy(bs);
   };
@@ -1237,8 +1352,8 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
     TRY(enter(ctxs[0], hip_stream));
     std::vector<Solver> S;
     S.reserve(n);
-    std::vector<double> res(n), target(n), best(n, INFINITY);
-    std::vector<int> stall(n, 0), cur(n, 1), status(n, SOCFV_NOT_CONVERGED), done(n, 0);
+    std::vector<double> res(n), target(n);
+    std::vector<int> cur(n, 1), status(n, SOCFV_NOT_CONVERGED), done(n, 0);
     std::vector<double> out(NV);
     for (int i = 0; i < n; ++i) {
       S.push_back(Solver{ctxs[i], &p[i]});
@@ -1260,12 +1375,19 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
     // the two-sweep z chunk comes from the same rounds x planes cost model as one problem's.
     bool any_kappa = false;
     for (int i = 0; i < n; ++i) any_kappa = any_kappa || ctxs[i]->kappa != nullptr;
-    std::vector<int> two(n, 0);
+    std::vector<int> two(n, 0), tw(n, 1), trx(n, 64);
     int n_two = 0;
     for (int i = 0; i < n; ++i) {
       two[i] = !any_kappa && two_path(ctxs[i]->g) && ctxs[i]->tiles.two;
       n_two += two[i];
+      // item shape: two cells per lane for even nx (one for odd), and the row-segment width
+      // with the lower cost of the lanes it computes per plane (one problem's rule)
+      const Grid &g = ctxs[i]->g;
+      tw[i] = two_w(g);
+      trx[i] = pick_rx(g.nx, g.ny, tw[i]);
     }
+    HIPCHK(hipMalloc(&d_ctl, sizeof(SolveCtl) * n));
+    HIPCHK(hipHostMalloc(&h_ctl, sizeof(SolveCtl) * n, hipHostMallocDefault));
     int dev = 0, ncu = 256;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1283,8 +1405,9 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
           if (!two[i] || !act[i]) continue;
           const Grid &g = ctxs[i]->g;
           const int zz = std::min(z, g.nz);
-          const int ox = 62 * two_w(g);
-          items += (long long)((g.nx + ox - 1) / ox) * ((g.ny + 13) / 14) * ((g.nz + zz - 1) / zz);
+          int gx, gy;
+          tile2_xy(g.nx, g.ny, tw[i], trx[i], gx, gy);
+          items += (long long)gx * gy * ((g.nz + zz - 1) / zz);
         }
         const long long cost = (items + ncu - 1) / ncu * (z + 2);
         if (best_cost < 0 || cost < best_cost) { best_cost = cost; zbest = z; }
@@ -1306,9 +1429,14 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
         b.r0 = c->r0;
         b.dt = (float)S[i].dt; b.Da = (float)p[i].Da; b.s_in = (float)p[i].s_in;
         b.s_eq = (float)p[i].s_eq; b.lo = S[i].lo; b.hi = S[i].hi; b.pinned = S[i].pinned;
+        b.w = tw[i];
+        b.rx = trx[i];
+        b.two = two[i];
+        b.ctl = d_ctl + i;
+        b.rpart = c->partial;
+        b.rnblk = march64_blocks(c->g);
         if (two[i]) {
-          const int ox = 62 * two_w(c->g);
-          b.gx = (c->g.nx + ox - 1) / ox; b.gy = (c->g.ny + 13) / 14;
+          tile2_xy(c->g.nx, c->g.ny, tw[i], trx[i], b.gx, b.gy);
           b.zc = std::min(zc2, c->g.nz);
         } else {
           b.gx = (c->g.nx + 63) / 64; b.gy = (c->g.ny + ty - 1) / ty;
@@ -1420,15 +1548,40 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
       launch_fill_f32(ctxs[i]->s32[0], ctxs[i]->g.n, 0.0f, bs);
       launch_fill_f32(ctxs[i]->s32[1], ctxs[i]->g.n, 0.0f, bs);
     }
-    // capture one chunk of K sweeps, K a multiple of 4: per pair of sweeps one two-sweep
-    // launch (its buffers flip once) and two single-sweep launches (theirs flip twice), so
-    // after K sweeps every problem's correction is back in s32[0]; partials on the last
-    // launches, then per-problem sums
+    // Each problem's loop runs on the device (SolveCtl, as one problem's solve): one chunk of
+    // K sweeps, K a multiple of 4, is captured as a graph: the work lists of the problems
+    // still sweeping, their corrections zeroed where a cycle starts, the sweeps (per pair of
+    // sweeps one two-sweep launch, whose buffers flip once, and two single-sweep launches,
+    // whose buffers flip twice, so after K sweeps every correction is back in s32[0]; partials
+    // on the last launches), per-problem sums, each problem's decision, the refreshes asked
+    // for (one gated launch per problem), and each refreshed problem's stop rule.  The host
+    // replays the graph a few times between reads of the states, and re-tiles the remaining
+    // problems when some have finished.
     int K = 4;
     for (int i = 0; i < n; ++i) K = std::max(K, S[i].chunk_len());
     K = (K + 3) / 4 * 4;
+    for (int i = 0; i < n; ++i) {
+      SolveCtl &h = h_ctl[i];
+      h = SolveCtl{};
+      h.state = done[i] ? CTL_DONE : CTL_RUN;
+      h.fill = 0;                        // zeroed above
+      h.cur = cur[i];
+      h.max_iter = p[i].max_iter;
+      h.tol = p[i].tol;
+      h.tau = S[i].tau;
+      h.npore = (double)ctxs[i]->npore;
+      h.reduction = CYCLE_REDUCTION;
+      h.target = target[i];
+      h.best = INFINITY;
+      h.res = res[i];
+      h.ri = INFINITY;
+    }
+    HIPCHK(hipMemcpyAsync(d_ctl, h_ctl, sizeof(SolveCtl) * n, hipMemcpyHostToDevice, bs));
     HIPCHK(hipStreamSynchronize(bs));
     HIPCHK(hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal));
+    launch_batch_control(d_probs, n, d_work, (int)max_tiles, d_nwork, BATCH_WORKLIST, nullptr, 0,
+                         bs);
+    launch_batch_control(d_probs, n, d_work, (int)max_tiles, d_nwork, BATCH_FILL, nullptr, 0, bs);
     for (int j = 0; j < K / 2; ++j) {
       const bool lastp = j == K / 2 - 1;
       if (n_two_tiles)
@@ -1442,19 +1595,44 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
       }
     }
     launch_batch_reduce(d_probs, n, d_part, d_out, bs);
+    launch_batch_control(d_probs, n, d_work, (int)max_tiles, d_nwork, BATCH_CHUNK, d_out, K, bs);
+    for (int i = 0; i < n; ++i) {
+      socfv_ctx *c = ctxs[i];
+      RefreshArgs a;
+      a.g = c->g; a.flags = c->flags; a.w = faces64(c); a.kappa = c->kappa;
+      a.s64 = nullptr; a.delta = c->s32[0]; a.s64_new = nullptr; a.r0 = c->r0;
+      a.s_in = p[i].s_in; a.s_eq = p[i].s_eq; a.Da = p[i].Da; a.pinned = S[i].pinned;
+      a.lo = S[i].lo; a.hi = S[i].hi; a.partial = c->partial; a.zc = S[i].t.zc;
+      launch_refresh_gated(a, c->s64[0], c->s64[1], d_ctl + i, bs);
+    }
+    launch_batch_control(d_probs, n, d_work, (int)max_tiles, d_nwork, BATCH_REFRESH, nullptr, 0,
+                         bs);
     HIPCHK(hipStreamEndCapture(bs, &graph));
     HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    std::vector<long> it(n, 0);
-    bool changed = false;
+    int planned = 0;                     // problems sweeping at the last tiling
+    for (int i = 0; i < n; ++i) planned += !done[i];
+    int nact = planned;
     for (;;) {
-      int nact = 0;
-      for (int i = 0; i < n; ++i) nact += !done[i];
+      // chunks between reads of the states: four while many problems sweep, one near the
+      // end (a launch after the last stop still dispatches its blocks, and the tail gains
+      // from re-tiling soon after each finish)
+      const int replays = nact > 4 ? 4 : 1;
+      for (int g = 0; g < replays; ++g) HIPCHK(hipGraphLaunch(exec, bs));
+      HIPCHK(hipMemcpyAsync(h_ctl, d_ctl, sizeof(SolveCtl) * n, hipMemcpyDeviceToHost, bs));
+      HIPCHK(hipStreamSynchronize(bs));
+      std::vector<int> act(n, 0);
+      nact = 0;
+      for (int i = 0; i < n; ++i) {
+        if (h_ctl[i].state == CTL_DIVERGED)
+          return fail(SOCFV_DIVERGED, "batch problem %d diverged at sweep %lld", i, h_ctl[i].it);
+        act[i] = h_ctl[i].state == CTL_RUN;
+        nact += act[i];
+      }
       if (!nact) break;
-      if (changed) {
+      if (nact < planned) {
         // fewer problems left: shorter chunks for more items; single-sweep chunks halved
-        // while their items are fewer than the persistent blocks
-        std::vector<int> act(n);
-        for (int i = 0; i < n; ++i) act[i] = !done[i];
+        // while their items are fewer than the persistent blocks (the next chunk's work
+        // lists come from the new table)
         zc2 = pick_zc2(act);
         auto tiles1 = [&](int zc) {
           long long m = 0;
@@ -1468,45 +1646,18 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
         build(bty, bzc, hp, tp);
         HIPCHK(hipMemcpyAsync(d_probs, hp.data(), sizeof(BatchProb) * n, hipMemcpyHostToDevice, bs));
         HIPCHK(hipMemcpyAsync(d_tiles, tp.data(), sizeof(int) * tp.size(), hipMemcpyHostToDevice, bs));
-        TRY(upload_work(hp, done));
-        changed = false;
+        planned = nact;
       }
-      HIPCHK(hipGraphLaunch(exec, bs));
-      HIPCHK(hipMemcpyAsync(h_out, d_out, sizeof(double) * NV * n, hipMemcpyDeviceToHost, bs));
-      HIPCHK(hipStreamSynchronize(bs));
-      for (int i = 0; i < n; ++i) {
-        if (done[i]) continue;
-        S[i].it += K;
-        S[i].it32 += K;
-        const double ri = S[i].res_of(h_out[NV * i]);
-        if (!std::isfinite(ri) || h_out[NV * i + 1] > 0)
-          return fail(SOCFV_DIVERGED, "batch problem %d diverged at sweep %ld", i, S[i].it);
-        bool refresh = ri < target[i] || S[i].it >= p[i].max_iter;
-        if (!refresh) {
-          if (ri < 0.999 * best[i]) { best[i] = ri; stall[i] = 0; }
-          else if (++stall[i] >= 8) refresh = true;
-        }
-        if (!refresh) continue;
-        TRY(S[i].refresh(cur[i], cur[i] ^ 1, ctxs[i]->s32[0], out.data()));
-        cur[i] ^= 1;
-        ++S[i].cycles;
-        res[i] = S[i].res_of(out[0]);
-        TRY(S[i].check(out.data(), res[i]));
-        best[i] = INFINITY;
-        stall[i] = 0;
-        if (res[i] < p[i].tol) {
-          done[i] = 1;
-          status[i] = SOCFV_OK;
-          changed = true;
-        } else if (S[i].it >= p[i].max_iter) {
-          done[i] = 1;
-          changed = true;
-        } else {
-          target[i] = std::fmax(p[i].tol, CYCLE_REDUCTION * res[i]);
-          launch_fill_f32(ctxs[i]->s32[0], ctxs[i]->g.n, 0.0f, bs);
-          launch_fill_f32(ctxs[i]->s32[1], ctxs[i]->g.n, 0.0f, bs);
-        }
-      }
+    }
+    for (int i = 0; i < n; ++i) {
+      const SolveCtl &h = h_ctl[i];
+      S[i].it += h.it;
+      S[i].it32 += h.it;
+      S[i].cycles += h.cycles;
+      S[i].it64 += h.cycles;
+      cur[i] = h.cur;
+      res[i] = h.res;
+      status[i] = h.state == CTL_DONE ? SOCFV_OK : SOCFV_NOT_CONVERGED;
     }
     // FP64 polish, outputs and states per problem
     for (int i = 0; i < n; ++i) {
@@ -1604,7 +1755,7 @@ int socfv_solve_stokes(socfv_ctx *c, const socfv_flow_params *p, double *ux, dou
     double **cellv[6] = {&a.p, &a.r, &a.z, &a.q, &a.d[0], &a.d[1]};
     for (double **v : cellv) TRY(alloc((void **)v, sizeof(double) * (size_t)n));
     TRY(alloc((void **)&a.ccode, (size_t)n));
-    const long long npart = 5ll * a.nbc + 6ll * a.nbf + 4ll * a.nbc + FS_N;
+    const long long npart = 6ll * a.nbc + 6ll * a.nbf + 4ll * a.nbc + FS_N;
     double *part = nullptr;
     TRY(alloc((void **)&part, sizeof(double) * (size_t)npart));
     a.prz[0] = part;
@@ -1614,7 +1765,8 @@ int socfv_solve_stokes(socfv_ctx *c, const socfv_flow_params *p, double *ux, dou
     a.pdq = part + 4ll * a.nbc;
     a.pdu = part + 5ll * a.nbc;
     a.pdiv = a.pdu + 6ll * a.nbf;
-    a.sc = a.pdiv + 4ll * a.nbc;
+    a.pfl = a.pdiv + 4ll * a.nbc;
+    a.sc = a.pfl + a.nbc;
     TRY(enter(c, hip_stream));
     // start from rest with zero pressure, or resume from the caller's velocity and pressure;
     // zero partials make the first step's CG run to its cap

@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(FB) k_flow_cg_init(FlowArgs a) {
     }
   }
   const long long sy = g.nx, sz = (long long)g.nx * g.ny;
-  double rz = 0.0, rr = 0.0;
+  double rz = 0.0, rr = 0.0, fl = 0.0;
   for (long long c = (long long)xcd_block(blockIdx.x, gridDim.x) * FB + threadIdx.x; c < g.n;
        c += (long long)gridDim.x * FB) {
     const unsigned cc = a.ccode[c];
@@ -265,17 +265,28 @@ __global__ void __launch_bounds__(FB) k_flow_cg_init(FlowArgs a) {
       zv = rv / pr.diag;
       rz += rv * zv;
       rr += rv * rv;
+      const double dp = pr.diag * a.p[c];
+      fl += b * b + dp * dp;
     }
     a.r[c] = rv;
     a.z[c] = zv;
   }
   rz = block_total(rz, false, sh);
   rr = block_total(rr, false, sh);
+  fl = block_total(fl, false, sh);
   if (threadIdx.x == 0) {
     a.prz[0][blockIdx.x] = rz;
     a.prr[0][blockIdx.x] = rr;
+    a.pfl[blockIdx.x] = fl;
   }
 }
+
+// Floor of the CG stop target: about what the recursively updated residual reaches in FP64,
+// (CG_FLOOR eps)^2 (||b||^2 + ||diag p||^2) at the step's start.  Near the steady state the
+// target (theta times the last velocity change) falls with the change; the floor keeps a
+// target below rounding level from running the CG to the per-step cap.  It binds only there
+// (the step's fixed point does not depend on it).
+constexpr double CG_FLOOR = 16.0;
 
 // iteration j, first half: stop test; d = z + beta d_old; q = A d; partials of d.q
 __global__ void __launch_bounds__(FB) k_flow_cg_a(FlowArgs a, int j) {
@@ -285,7 +296,9 @@ __global__ void __launch_bounds__(FB) k_flow_cg_a(FlowArgs a, int j) {
   const int par = j & 1;
   const double rz = sum_partials(a.prz[par], a.nbc, 1, sh);
   const double rr = sum_partials(a.prr[par], a.nbc, 1, sh);
-  if (rr <= a.sc[FS_TARGET]) {
+  const double floor2 = (CG_FLOOR * 2.220446049250313e-16) * (CG_FLOOR * 2.220446049250313e-16) *
+                        sum_partials(a.pfl, a.nbc, 1, sh);
+  if (rr <= fmax(a.sc[FS_TARGET], floor2)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) a.sc[FS_DONE] = 1.0;
     return;
   }

@@ -43,6 +43,8 @@ struct SweepArgs {
   double lo, hi;        // bound check on the written state (ignored for corrections)
   double *partial;      // nullable: per-block [sum R^2, violations, sum R, -]
   int zc;               // z cells per block
+  const int *gate = nullptr;  // nullable: the launch returns at once unless *gate == 0
+                              // (device-side stop of the solve loop)
 };
 
 // FP64 residual refresh for the defect correction:
@@ -94,9 +96,12 @@ struct AdjRefreshArgs {
   int zc;
 };
 
+struct SolveCtl;
+
 // One problem of a batched launch (device table entry).
 struct BatchProb {
   int nx, ny, nz;
+  int w, rx;            // two-sweep items: cells per lane, lanes per row segment
   const uint8_t *flags;
   const float *wx, *wy, *wz, *wxo;
   const float *kappa;
@@ -106,8 +111,12 @@ struct BatchProb {
   double lo, hi;
   int pinned;
   int gx, gy, gz, zc;   // tile grid of this problem: 64 x ty lanes x zc planes, or for the
-                        // two-sweep path 124 x 14 output cells x zc planes
+                        // two-sweep path tiles of shape (w, rx) (tile2_xy) x zc planes
   int tile0;            // index of its first tile in the work list
+  int two;              // items of the two-sweep kernel (else of the single-sweep one)
+  SolveCtl *ctl;        // device-side loop state of this problem
+  const double *rpart;  // its refresh partials (rnblk blocks)
+  int rnblk;
 };
 
 // work: tile numbers of the unfinished problems; *nwork (device) their count
@@ -137,7 +146,29 @@ struct Tiles {
   int zc;   // z cells marched per block
   int zc2;  // z cells per block of the two-sweep kernel
   int two;  // FP32 sweeps two per launch (shapes below 2^30 cells)
+  int rx = 64;  // two-sweep tiles: lanes per row segment (64: one row per wave; 32: two)
 };
+
+// Two-sweep tiles: a block of 1024 lanes holds rows of rx lanes (rx = 64: 16 rows of one wave
+// each; rx = 32: 32 rows, two per wave), w cells per lane, and writes its interior
+// (rx - 2) w x (1024 / rx - 2) cells.  gx, gy: tiles along x and y.
+inline void tile2_xy(int nx, int ny, int w, int rx, int &gx, int &gy) {
+  const int ox = (rx - 2) * w, oy = 1024 / rx - 2;
+  gx = (nx + ox - 1) / ox;
+  gy = (ny + oy - 1) / oy;
+}
+
+// Relative cost per lane of 32-lane rows against 64-lane rows, measured on the 1024 x 512 x 256
+// slab (10% longer per lane: a wave's loads span two rows).
+constexpr double RX32_COST = 1.10;
+
+// The row-segment width with the lower cost of the lanes it computes per plane (ties: 64).
+inline int pick_rx(int nx, int ny, int w) {
+  int ax, ay, bx, by;
+  tile2_xy(nx, ny, w, 64, ax, ay);
+  tile2_xy(nx, ny, w, 32, bx, by);
+  return RX32_COST * bx * by < (double)ax * ay ? 32 : 64;
+}
 
 // Explicit Nernst model (FP64): transport step on every pore cell; electrode (reactive)
 // cells take sigma(V - eta) with eta relaxed toward the overpotential balancing the
@@ -177,6 +208,7 @@ struct FlowArgs {
   double *prz[2], *prr[2], *pdq;  // per-block CG partials (cell kernels), ping-pong by parity
   double *pdu;           // per-block [sum du^2, sum u^2] of the projection, (3 nbf) x 2
   double *pdiv;          // per-block [max |div u|, inlet flux] (cell kernels), nbc x 2
+  double *pfl;           // per-block sum of b^2 + (diag p)^2 of the CG start (the floor)
   double *sc;            // FlowSlot scalars
 };
 int flow_cell_blocks(const Grid &g);
@@ -245,6 +277,43 @@ void launch_gradients(const Grid &g, const uint8_t *flags, Faces<double> w, cons
 // deterministic second pass: out[k] = sum (or max if bit k of maxmask) over blocks
 void launch_reduce(const double *partial, int nblk, int nv, unsigned maxmask, double *out,
                    hipStream_t st);
+
+// Device-side control of the FP32 correction solve: the stop rule and the refresh decision of
+// every chunk of sweeps are taken on the device, so the host enqueues many chunks between two
+// reads of the state.  Sweeps run while state == CTL_RUN; the refresh while CTL_REFRESH; the
+// corrections are zeroed before a chunk while `fill` is set.
+enum { CTL_RUN = 0, CTL_REFRESH = 1, CTL_DONE = 2, CTL_STOP = 3, CTL_DIVERGED = 4 };
+struct SolveCtl {
+  int state;            // CTL_*
+  int fill;             // zero the corrections before the next chunk
+  int cur;              // s64 buffer holding the state
+  int stall;            // chunks without a 0.1% residual decrease
+  long long it;         // FP32 sweeps done
+  long long max_iter;
+  int cycles;           // refreshes after the first
+  int pad;
+  double tol, tau, npore, reduction;   // stop tolerance, time scale, pore cells, per-cycle drop
+  double target, best, res, ri;        // cycle target, best correction residual, last FP64 /
+                                       // correction residual
+};
+// after a chunk of k sweeps (its last launch wrote nblk x NV partials): the correction
+// residual, the iteration count, the cycle's stop test (refresh when due)
+void launch_ctl_chunk(SolveCtl *ctl, const double *partial, int nblk, int k, hipStream_t st);
+// after the (gated) refresh: the FP64 residual, the stop rule of the solve, the next cycle
+void launch_ctl_refresh(SolveCtl *ctl, const double *partial, int nblk, hipStream_t st);
+// The batched loop on the device: BATCH_WORKLIST rebuilds the work lists from the problems'
+// states; BATCH_FILL zeroes the corrections of the problems that start a cycle; BATCH_CHUNK
+// takes every sweeping problem's decision from the reduced partials `out` of a chunk of k
+// sweeps; BATCH_REFRESH applies the stop rule after the problems' gated refreshes.
+enum { BATCH_WORKLIST = 0, BATCH_FILL = 1, BATCH_CHUNK = 2, BATCH_REFRESH = 3 };
+void launch_batch_control(const BatchProb *probs, int n, int *work, int max_tiles, int *nwork,
+                          int which, const double *out, int k, hipStream_t st);
+// the refresh of the correction, gated on state == CTL_REFRESH, reading s64[ctl->cur] (+ delta)
+// and writing s64[ctl->cur ^ 1]
+void launch_refresh_gated(const RefreshArgs &a, double *s64_0, double *s64_1,
+                          const SolveCtl *ctl, hipStream_t st);
+// zero two FP32 buffers of n values when ctl->fill is set
+void launch_fill_gated(float *a, float *b, long long n, const SolveCtl *ctl, hipStream_t st);
 
 // Static scratch of the allocation-free entry point: SCRATCH_DOUBLES doubles of device memory
 // per GPU.  scratch_address gives its device address on device dev (which must be current at

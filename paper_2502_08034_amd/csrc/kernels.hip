@@ -339,6 +339,7 @@ dim3 sweep_grid(const Grid &g, const Tiles &t) {
 
 template <typename T, bool DC, bool RES>
 __global__ void __launch_bounds__(1024) k_sweep(SweepArgs<T> a) {
+  if (a.gate && *a.gate != CTL_RUN) return;
   const Grid g = a.g;
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -411,15 +412,17 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 template <bool DC, bool RES, bool ACT>
 __global__ void __launch_bounds__(1024) k_sweep_v4(SweepArgs<float> a, int gx, int gy, int gz);
 
-// Two sweeps per launch (time skewing along the z march).  A block of 64 x 16 lanes holds
-// a (64 W) x 16 tile, W consecutive x cells per lane (W = 2 for even nx, 1 for odd), and
-// writes the second sweep on its interior (62 W) x 14 cells; tiles overlap by one lane in x
-// and one row in y on each side, where the first sweep is recomputed.  Marching plane j,
+// Two sweeps per launch (time skewing along the z march).  A block of 1024 lanes holds a
+// tile of rows of RX lanes (RX = 64: 16 rows, one per wave; RX = 32: 32 rows, two per wave,
+// which fits narrow boxes with less waste), W consecutive x cells per lane (W = 2 for even nx,
+// 1 for odd), and writes the second sweep on its interior (RX - 2) W x (1024 / RX - 2) cells;
+// tiles overlap by one lane in x and one row in y on each side, where the first sweep is
+// recomputed.  Marching plane j,
 // the block computes the first sweep s1(j) from s(j-1..j+1) over the whole tile, stages
 // s1(j) in LDS (two plane slots, one barrier per plane), and the second sweep at plane j-1
 // from s1(j-2..j).  State, velocities, flags and the frozen residual come from HBM once for
 // two sweeps.  Each sweep is the arithmetic of one k_sweep_v4 sweep, cell by cell.
-constexpr int T2_ROWS = 16, T2_OUT_Y = 14;
+constexpr int T2_ROWS = 16;   // thread rows of a two-sweep block (64 x 16 = 1024 lanes)
 
 template <int W>
 struct VecW {
@@ -670,10 +673,10 @@ __device__ __forceinline__ void sto(float *base, unsigned off, const VecW<W> &v)
 // then selects for the wall velocities that must be zero.  With UPZ the plane's upper
 // z-face velocity is loaded too; without, the caller takes it from the next plane's lower
 // face.
-template <bool DC, bool UPZ, bool ACT, int W>
+template <bool DC, bool UPZ, bool ACT, int W, int RX>
 __device__ __forceinline__ void load_plane2(const SweepArgs<float> &a, PlaneW<W> &d,
                                             unsigned ib, unsigned pl, int j, int xc, int yc,
-                                            int lane, bool last, bool yl, bool yr) {
+                                            int lx, bool last, bool yl, bool yr) {
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
   const int jj = min(j, nz - 1);
   const bool up = jj + 1 < nz;
@@ -705,28 +708,31 @@ __device__ __forceinline__ void load_plane2(const SweepArgs<float> &a, PlaneW<W>
   d.left = a.s_in;
   d.right = 0.f;
   d.c.wxr = 0.f;
-  if (lane == 0 && xc > 0) d.left = ldo1(a.s, o4 - 4u);
+  if (lx == 0 && xc > 0) d.left = ldo1(a.s, o4 - 4u);
   if (last) d.c.wxr = ldo1(a.w.wxo, 4u * (yc + (unsigned)ny * (unsigned)jj));
-  else if (lane == 63) {
+  else if (lx == RX - 1) {
     d.right = ldo1(a.s, o4 + 4u * W);
     d.c.wxr = ldo1(a.w.wx, o4 + 4u * W);
   }
 }
 
-template <bool DC, bool RES, bool ACT, bool ADJ, int W>
+template <bool DC, bool RES, bool ACT, bool ADJ, int W, int RX>
 __device__ __forceinline__ void sweep2_tile(const SweepArgs<float> &a, int gx, int gy, int L,
-                                            float (*lds)[T2_ROWS][64 * W],
+                                            float (*lds)[1024 / RX][RX * W],
                                             float4 (*qlds)[2 * W][64 * T2_ROWS], double *part) {
+  constexpr int RY = 1024 / RX;
   const Grid g = a.g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int bx = L % gx, by = (L / gx) % gy, bz = L / (gx * gy);
-  const int lane = threadIdx.x, row = threadIdx.y, tid = lane + 64 * row;
-  const int x = bx * (62 * W) - W + W * lane;
-  const int y = by * T2_OUT_Y - 1 + row;
+  const int lane = threadIdx.x, tid = lane + 64 * threadIdx.y;
+  // position in the tile: lane lx of row ry (RX = 64: the wave's lane and the wave's row)
+  const int lx = tid % RX, row = tid / RX;
+  const int x = bx * ((RX - 2) * W) - W + W * lx;
+  const int y = by * (RY - 2) - 1 + row;
   const int z0 = bz * a.zc;
   const int z1 = min(z0 + a.zc, nz);
   const bool act = x >= 0 && x < nx && y >= 0 && y < ny;
-  const bool outc = act && lane >= 1 && lane <= 62 && row >= 1 && row <= T2_ROWS - 2;
+  const bool outc = act && lx >= 1 && lx <= RX - 2 && row >= 1 && row <= RY - 2;
   const int xc = min(max(x, 0), nx - W);
   const int yc = min(max(y, 0), ny - 1);
   const bool yl = yc > 0, yr = yc < ny - 1;
@@ -748,18 +754,19 @@ __device__ __forceinline__ void sweep2_tile(const SweepArgs<float> &a, int gx, i
   VecW<W> sdn;                           // s(j-1)
   // first-sweep planes below the box are closed walls: their LDS copy must be finite
 #pragma unroll
-  for (int k = 0; k < W; ++k) lds[0][row][W * lane + k] = lds[1][row][W * lane + k] = 0.f;
+  for (int k = 0; k < W; ++k) lds[0][row][W * lx + k] = lds[1][row][W * lx + k] = 0.f;
   {
     const unsigned o = ib + pl * (unsigned)jb;
     sdn = jb > 0 ? ldo<W>(a.s, 4u * (o - pl)) : zw;
     P[3].s_up = ldo<W>(a.s, 4u * o);     // s(jb)
     P[3].c.fl = 0u;
-    load_plane2<DC, PD == 1, ACT>(a, P[0], ib, pl, jb, xc, yc, lane, last, yl, yr);
-    if (PD == 2) load_plane2<DC, false, ACT>(a, P[1], ib, pl, jb + 1, xc, yc, lane, last, yl, yr);
+    load_plane2<DC, PD == 1, ACT, W, RX>(a, P[0], ib, pl, jb, xc, yc, lx, last, yl, yr);
+    if (PD == 2)
+      load_plane2<DC, false, ACT, W, RX>(a, P[1], ib, pl, jb + 1, xc, yc, lx, last, yl, yr);
   }
   auto step = [&](PlaneW<W> &cur, const PlaneW<W> &prev, const PlaneW<W> &nxt, PlaneW<W> &ld,
                   int j) {
-    load_plane2<DC, PD == 1, ACT>(a, ld, ib, pl, j + PD, xc, yc, lane, last, yl, yr);
+    load_plane2<DC, PD == 1, ACT, W, RX>(a, ld, ib, pl, j + PD, xc, yc, lx, last, yl, yr);
     if (PD == 2) {
       // upper z face of plane j = lower z face of plane j+1 (closed above the top plane)
 #pragma unroll
@@ -769,8 +776,9 @@ __device__ __forceinline__ void sweep2_tile(const SweepArgs<float> &a, int gx, i
     float left = lane_from_below(s_c.v[W - 1]);
     float right = lane_from_above(s_c.v[0]);
     float wxr = lane_from_above(cur.c.wx.v[0]);
-    if (lane == 0) left = cur.left;
-    if (lane == 63 || last) {
+    // the segment's edge lanes take what they loaded (the shifts cross segments there)
+    if (lx == 0) left = cur.left;
+    if (lx == RX - 1 || last) {
       right = cur.right;
       wxr = cur.c.wxr;
     }
@@ -793,7 +801,7 @@ __device__ __forceinline__ void sweep2_tile(const SweepArgs<float> &a, int gx, i
     const int bp = p & 1;
     VecW<W> c1;
 #pragma unroll
-    for (int k = 0; k < W; ++k) c1.v[k] = lds[bp][row][W * lane + k];
+    for (int k = 0; k < W; ++k) c1.v[k] = lds[bp][row][W * lx + k];
     const float c1_left = lane_from_below(c1.v[W - 1]);
     const float c1_right = lane_from_above(c1.v[0]);
     if (p >= z0 && p < z1 && outc) {
@@ -802,9 +810,9 @@ __device__ __forceinline__ void sweep2_tile(const SweepArgs<float> &a, int gx, i
       VecW<W> ym1, yp1, dn1;
 #pragma unroll
       for (int k = 0; k < W; ++k) {
-        ym1.v[k] = lds[bp][row - 1][W * lane + k];
-        yp1.v[k] = lds[bp][row + 1][W * lane + k];
-        dn1.v[k] = lds[bp ^ 1][row][W * lane + k];
+        ym1.v[k] = lds[bp][row - 1][W * lx + k];
+        yp1.v[k] = lds[bp][row + 1][W * lx + k];
+        dn1.v[k] = lds[bp ^ 1][row][W * lx + k];
       }
       const float lft = x == 0 ? a.s_in : c1_left;
       const float rgt = c1_right;
@@ -830,7 +838,7 @@ __device__ __forceinline__ void sweep2_tile(const SweepArgs<float> &a, int gx, i
       }
     }
 #pragma unroll
-    for (int k = 0; k < W; ++k) lds[j & 1][row][W * lane + k] = s1_j.v[k];
+    for (int k = 0; k < W; ++k) lds[j & 1][row][W * lx + k] = s1_j.v[k];
     __syncthreads();
   };
   for (int j = jb; j <= je; j += 4) {
@@ -846,17 +854,19 @@ __device__ __forceinline__ void sweep2_tile(const SweepArgs<float> &a, int gx, i
 }
 
 // One tile march per block; tiles go to workgroups XCD by XCD.
-template <bool DC, bool RES, bool ACT, bool ADJ, int W>
+template <bool DC, bool RES, bool ACT, bool ADJ, int W, int RX>
 __global__ void __launch_bounds__(1024) k_sweep2(SweepArgs<float> a, int gx, int gy, int gz) {
-  __shared__ float lds[2][T2_ROWS][64 * W];
+  __shared__ float lds[2][1024 / RX][RX * W];
   __shared__ float4 qlds[2][2 * W][64 * T2_ROWS];
+  if (a.gate && *a.gate != CTL_RUN) return;
   const int L = xcd_tile(blockIdx.x, gx * gy * gz);
-  sweep2_tile<DC, RES, ACT, ADJ, W>(a, gx, gy, L, lds, qlds,
-                                    RES ? a.partial + (long long)NV * blockIdx.x : nullptr);
+  sweep2_tile<DC, RES, ACT, ADJ, W, RX>(a, gx, gy, L, lds, qlds,
+                                        RES ? a.partial + (long long)NV * blockIdx.x : nullptr);
 }
 
 template <bool DC, bool RES, bool ACT>
 __global__ void __launch_bounds__(1024) k_sweep_v4(SweepArgs<float> a, int gx, int gy, int gz) {
+  if (a.gate && *a.gate != CTL_RUN) return;
   constexpr int W = 4;
   const Grid g = a.g;
   const int nx = g.nx, ny = g.ny;
@@ -956,10 +966,9 @@ bool two_path(const Grid &g) { return g.n < (1ll << 30); }
 int two_w(const Grid &g) { return (g.nx & 1) ? 1 : 2; }
 
 dim3 sweep2_grid(const Grid &g, const Tiles &t) {
-  const int ox = 62 * two_w(g);
-  return dim3((unsigned)((g.nx + ox - 1) / ox),
-              (unsigned)((g.ny + T2_OUT_Y - 1) / T2_OUT_Y),
-              (unsigned)((g.nz + t.zc2 - 1) / t.zc2));
+  int gx, gy;
+  tile2_xy(g.nx, g.ny, two_w(g), t.rx, gx, gy);
+  return dim3((unsigned)gx, (unsigned)gy, (unsigned)((g.nz + t.zc2 - 1) / t.zc2));
 }
 
 // Calls f with three std::bool_constant arguments, so one launch line covers the eight
@@ -983,23 +992,33 @@ void launch_sweep2(const SweepArgs<float> &a, const Tiles &t, hipStream_t st, bo
   SweepArgs<float> b = a;
   b.zc = t.zc2;
   dim3 block(64, T2_ROWS, 1);
-  auto go = [&](auto w) {
-    constexpr int W = decltype(w)::value;
+  auto go = [&](auto w, auto rx) {
+    constexpr int W = decltype(w)::value, RX = decltype(rx)::value;
     if (adj) {
       // transpose sweeps run only in the correction form
       with_flags(true, a.partial != nullptr, a.kappa != nullptr, [&](auto, auto res, auto act) {
-        k_sweep2<true, res.value, act.value, true, W><<<nb, block, 0, st>>>(b, gv.x, gv.y, gv.z);
+        k_sweep2<true, res.value, act.value, true, W, RX><<<nb, block, 0, st>>>(b, gv.x, gv.y,
+                                                                               gv.z);
       });
       return;
     }
     with_flags(a.r0 != nullptr, a.partial != nullptr, a.kappa != nullptr,
                [&](auto dc, auto res, auto act) {
-                 k_sweep2<dc.value, res.value, act.value, false, W><<<nb, block, 0, st>>>(
+                 k_sweep2<dc.value, res.value, act.value, false, W, RX><<<nb, block, 0, st>>>(
                      b, gv.x, gv.y, gv.z);
                });
   };
-  if (two_w(a.g) == 2) go(std::integral_constant<int, 2>{});
-  else go(std::integral_constant<int, 1>{});
+  using I2 = std::integral_constant<int, 2>;
+  using I1 = std::integral_constant<int, 1>;
+  using R64 = std::integral_constant<int, 64>;
+  using R32 = std::integral_constant<int, 32>;
+  if (two_w(a.g) == 2) {
+    if (t.rx == 32) go(I2{}, R32{});
+    else go(I2{}, R64{});
+  } else {
+    if (t.rx == 32) go(I1{}, R32{});
+    else go(I1{}, R64{});
+  }
 }
 
 dim3 sweep_grid_v4(const Grid &g, const Tiles &t) {
@@ -1143,10 +1162,10 @@ __global__ void __launch_bounds__(1024) k_batch_sweep2(const BatchProb *__restri
                                                       const int *__restrict__ work,
                                                       const int *__restrict__ nwork, int parity,
                                                       double *__restrict__ partial) {
-  // LDS for two cells per lane; a problem with odd nx (one cell per lane) uses a view of
-  // the same arrays at its smaller shape
-  __shared__ float lds[2][T2_ROWS][128];
-  __shared__ float4 qlds[2][4][64 * T2_ROWS];
+  // LDS for the largest item shape (two cells per lane); every (w, rx) shape uses a view of
+  // the same arrays
+  __shared__ float lds[2 * 1024 * 2];
+  __shared__ float4 qlds[2 * 4 * 64 * T2_ROWS];
   const int nw = *nwork;
   const int per = (nw + (int)gridDim.x - 1) / (int)gridDim.x;
   const int b = xcd_tile(blockIdx.x, gridDim.x);
@@ -1174,12 +1193,24 @@ __global__ void __launch_bounds__(1024) k_batch_sweep2(const BatchProb *__restri
     a.partial = nullptr;
     a.zc = q.zc;
     double *pp = RES ? partial + (long long)NV * t : nullptr;
-    if (q.nx & 1)
-      sweep2_tile<true, RES, false, false, 1>(
-          a, q.gx, q.gy, t - q.tile0, reinterpret_cast<float (*)[T2_ROWS][64]>(&lds[0][0][0]),
-          reinterpret_cast<float4 (*)[2][64 * T2_ROWS]>(&qlds[0][0][0]), pp);
-    else
-      sweep2_tile<true, RES, false, false, 2>(a, q.gx, q.gy, t - q.tile0, lds, qlds, pp);
+    const int lt = t - q.tile0;
+    auto item = [&](auto wc, auto rxc) {
+      constexpr int W = decltype(wc)::value, RX = decltype(rxc)::value;
+      sweep2_tile<true, RES, false, false, W, RX>(
+          a, q.gx, q.gy, lt, reinterpret_cast<float (*)[1024 / RX][RX * W]>(lds),
+          reinterpret_cast<float4 (*)[2 * W][64 * T2_ROWS]>(qlds), pp);
+    };
+    using I2 = std::integral_constant<int, 2>;
+    using I1 = std::integral_constant<int, 1>;
+    using R64 = std::integral_constant<int, 64>;
+    using R32 = std::integral_constant<int, 32>;
+    if (q.w == 2) {
+      if (q.rx == 32) item(I2{}, R32{});
+      else item(I2{}, R64{});
+    } else {
+      if (q.rx == 32) item(I1{}, R32{});
+      else item(I1{}, R64{});
+    }
   }
 }
 
@@ -1320,6 +1351,10 @@ struct March64Args {
   double lo, hi;        // bound check on the written state
   double *partial;      // per block: sweep / refresh NV values, outputs NV2 values
   int zc;
+  const int *gate;      // nullable: run only if *gate == gate_val
+  int gate_val;
+  const int *sel;       // nullable: s = pair[*sel], s_new = pair[*sel ^ 1]
+  double *pair[2];
 };
 
 template <int OP>
@@ -1337,6 +1372,12 @@ template <int W, int OP, bool RES, bool DELTA>
 __global__ void __launch_bounds__(64 * M64_ROWS) k_march64(March64Args a, int gx, int gy,
                                                              int gz) {
   constexpr int K = M64Acc<OP>::K;
+  if (a.gate && *a.gate != a.gate_val) return;
+  if (a.sel) {
+    const int c = *a.sel;
+    a.s = a.pair[c];
+    a.s_new = a.pair[c ^ 1];
+  }
   const Grid g = a.g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int L = xcd_tile(blockIdx.x, gx * gy * gz);
@@ -1522,6 +1563,191 @@ void launch_refresh(const RefreshArgs &r, const Tiles &, hipStream_t st) {
   a.partial = r.partial;
   if (r.delta) launch_march64<M64_REFRESH, true, true>(a, st);
   else launch_march64<M64_REFRESH, true, false>(a, st);
+}
+
+void launch_refresh_gated(const RefreshArgs &r, double *s64_0, double *s64_1,
+                          const SolveCtl *ctl, hipStream_t st) {
+  March64Args a{};
+  a.g = r.g; a.flags = r.flags; a.w = r.w; a.kappa = r.kappa;
+  a.delta = r.delta; a.r0 = r.r0;
+  a.s_in = r.s_in; a.s_eq = r.s_eq; a.Da = r.Da; a.pinned = r.pinned; a.lo = r.lo; a.hi = r.hi;
+  a.partial = r.partial;
+  a.gate = &ctl->state;
+  a.gate_val = CTL_REFRESH;
+  a.sel = &ctl->cur;
+  a.pair[0] = s64_0;
+  a.pair[1] = s64_1;
+  if (r.delta) launch_march64<M64_REFRESH, true, true>(a, st);
+  else launch_march64<M64_REFRESH, true, false>(a, st);
+}
+
+// ---- device-side control of the FP32 correction solve ---------------------------------
+
+// sums of partial values 0 (sum R^2) and 1 (violations) over nblk blocks, fixed order;
+// every thread returns them
+__device__ __forceinline__ void ctl_sums(const double *__restrict__ partial, int nblk,
+                                         double &ss, double &viol) {
+  __shared__ double sh[2][256];
+  double a = 0.0, b = 0.0;
+  for (int j = threadIdx.x; j < nblk; j += 256) {
+    a += partial[(long long)NV * j];
+    b += partial[(long long)NV * j + 1];
+  }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  ss = sh[0][0];
+  viol = sh[1][0];
+}
+
+// After a chunk of k correction sweeps whose last launch summed ss = sum R^2 and viol
+// (non-finite cells): the correction residual tau rms(r0 - A delta), then the cycle's end
+// test (target reached, max_iter, or no 0.1% decrease in 8 chunks).
+__device__ void ctl_after_chunk(SolveCtl *ctl, double ss, double viol, int k) {
+  ctl->fill = 0;
+  ctl->it += k;
+  const double ri = ctl->tau * sqrt(ss / ctl->npore);
+  ctl->ri = ri;
+  if (!isfinite(ri) || viol > 0.0) {
+    ctl->state = CTL_DIVERGED;
+    return;
+  }
+  bool refresh = ri < ctl->target || ctl->it >= ctl->max_iter;
+  if (!refresh) {
+    if (ri < 0.999 * ctl->best) {
+      ctl->best = ri;
+      ctl->stall = 0;
+    } else if (++ctl->stall >= 8) {
+      refresh = true;
+    }
+  }
+  if (refresh) ctl->state = CTL_REFRESH;
+}
+
+// After the refresh (ss, viol of the FP64 residual of s64 + delta): the solve's stop rule
+// (Eq. (convergence-bv-change)) and the next cycle's target.
+__device__ void ctl_after_refresh(SolveCtl *ctl, double ss, double viol) {
+  const double res = ctl->tau * sqrt(ss / ctl->npore);
+  ctl->res = res;
+  ctl->cycles += 1;
+  ctl->cur ^= 1;
+  if (!isfinite(res) || viol > 0.0) {
+    ctl->state = CTL_DIVERGED;
+  } else if (res < ctl->tol) {
+    ctl->state = CTL_DONE;
+  } else if (ctl->it >= ctl->max_iter) {
+    ctl->state = CTL_STOP;
+  } else {
+    ctl->target = fmax(ctl->tol, ctl->reduction * res);
+    ctl->best = INFINITY;
+    ctl->stall = 0;
+    ctl->fill = 1;
+    ctl->state = CTL_RUN;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_ctl_chunk(SolveCtl *ctl, const double *partial,
+                                                   int nblk, int k) {
+  if (ctl->state != CTL_RUN) return;
+  double ss, viol;
+  ctl_sums(partial, nblk, ss, viol);
+  if (threadIdx.x == 0) ctl_after_chunk(ctl, ss, viol, k);
+}
+
+__global__ void __launch_bounds__(256) k_ctl_refresh(SolveCtl *ctl, const double *partial,
+                                                     int nblk) {
+  if (ctl->state != CTL_REFRESH) return;
+  double ss, viol;
+  ctl_sums(partial, nblk, ss, viol);
+  if (threadIdx.x == 0) ctl_after_refresh(ctl, ss, viol);
+}
+
+// ---- the batched solve's loop on the device -------------------------------------------
+
+// Work lists of the problems still sweeping (state CTL_RUN): the tile numbers of every such
+// problem, two-sweep items at work[0..] and single-sweep items at work[max_tiles..], their
+// counts at nwork[0] and nwork[1].  One block; problems in order, tiles in order.
+__global__ void __launch_bounds__(256) k_batch_worklist(const BatchProb *__restrict__ probs,
+                                                        int n, int *__restrict__ work,
+                                                        int max_tiles, int *__restrict__ nwork) {
+  int m[2] = {0, 0};
+  for (int i = 0; i < n; ++i) {
+    const BatchProb &q = probs[i];
+    if (q.ctl->state != CTL_RUN) continue;
+    const int path = q.two ? 0 : 1;
+    const int nt = q.gx * q.gy * q.gz;
+    int *dst = work + (long long)path * max_tiles + m[path];
+    for (int t = threadIdx.x; t < nt; t += 256) dst[t] = q.tile0 + t;
+    m[path] += nt;
+  }
+  if (threadIdx.x == 0) {
+    nwork[0] = m[0];
+    nwork[1] = m[1];
+  }
+}
+
+// Zero the corrections of the problems that start a cycle (ctl->fill); 16 blocks per problem.
+__global__ void __launch_bounds__(256) k_batch_fill_gated(const BatchProb *__restrict__ probs) {
+  const BatchProb &q = probs[blockIdx.x / 16];
+  if (!q.ctl->fill) return;
+  const long long nc = (long long)q.nx * q.ny * q.nz;
+  for (long long i = (blockIdx.x % 16) * 256ll + threadIdx.x; i < nc; i += 16 * 256ll) {
+    q.s0[i] = 0.f;
+    q.s1[i] = 0.f;
+  }
+}
+
+// After a chunk of k sweeps: each sweeping problem's decision from its reduced partials
+// out[NV i ..] (k_batch_reduce); one thread per problem.
+__global__ void __launch_bounds__(64) k_batch_ctl_chunk(const BatchProb *__restrict__ probs,
+                                                        const double *__restrict__ out, int n,
+                                                        int k) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= n || probs[i].ctl->state != CTL_RUN) return;
+  ctl_after_chunk(probs[i].ctl, out[(long long)NV * i], out[(long long)NV * i + 1], k);
+}
+
+// After the (gated, per-problem) refreshes: block i applies problem i's stop rule from its
+// refresh partials.
+__global__ void __launch_bounds__(256) k_batch_ctl_refresh(const BatchProb *__restrict__ probs) {
+  const BatchProb &q = probs[blockIdx.x];
+  if (q.ctl->state != CTL_REFRESH) return;
+  double ss, viol;
+  ctl_sums(q.rpart, q.rnblk, ss, viol);
+  if (threadIdx.x == 0) ctl_after_refresh(q.ctl, ss, viol);
+}
+
+void launch_batch_control(const BatchProb *probs, int n, int *work, int max_tiles, int *nwork,
+                          int which, const double *out, int k, hipStream_t st) {
+  switch (which) {
+    case BATCH_WORKLIST:
+      k_batch_worklist<<<1, 256, 0, st>>>(probs, n, work, max_tiles, nwork);
+      break;
+    case BATCH_FILL:
+      k_batch_fill_gated<<<16 * n, 256, 0, st>>>(probs);
+      break;
+    case BATCH_CHUNK:
+      k_batch_ctl_chunk<<<(n + 63) / 64, 64, 0, st>>>(probs, out, n, k);
+      break;
+    default:
+      k_batch_ctl_refresh<<<n, 256, 0, st>>>(probs);
+      break;
+  }
+}
+
+void launch_ctl_chunk(SolveCtl *ctl, const double *partial, int nblk, int k, hipStream_t st) {
+  k_ctl_chunk<<<1, 256, 0, st>>>(ctl, partial, nblk, k);
+}
+
+void launch_ctl_refresh(SolveCtl *ctl, const double *partial, int nblk, hipStream_t st) {
+  k_ctl_refresh<<<1, 256, 0, st>>>(ctl, partial, nblk);
 }
 
 int outputs_blocks(const Grid &g) { return march64_blocks(g); }
@@ -1801,9 +2027,22 @@ int scratch_address(int dev, double **out) {
   return 0;
 }
 
+__global__ void __launch_bounds__(256) k_fill2_gated(float *a, float *b, long long n,
+                                                     const SolveCtl *ctl) {
+  if (!ctl->fill) return;
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += 256ll * gridDim.x) {
+    a[i] = 0.f;
+    b[i] = 0.f;
+  }
+}
+
 static unsigned fill_blocks(long long n) {
   long long b = (n + 255) / 256;
   return (unsigned)(b < 65536 ? (b > 0 ? b : 1) : 65536);
+}
+
+void launch_fill_gated(float *a, float *b, long long n, const SolveCtl *ctl, hipStream_t st) {
+  k_fill2_gated<<<fill_blocks(n), 256, 0, st>>>(a, b, n, ctl);
 }
 
 void launch_fill_f32(float *p, long long n, float v, hipStream_t st) {

@@ -6,6 +6,11 @@ from a ``--kernel-trace`` CSV, so that launches of one kernel on differently siz
 not averaged together; with ``--split-us`` each group is split into dispatches of at least T us
 and shorter ones (kernels that return at once once a device-side stop is set).
 
+``timeline CSV --window NAME [--bins B]``: GPU busy fraction and the launches of kernels
+whose name contains NAME, per time bin over the window from that kernel's first launch to
+its last (how a batched solve's launches shrink as problems finish, and whether the host
+leaves the GPU idle between them).
+
 ``pmc --fetch CSV --write CSV [--sq CSV] --kernel NAME --cells N --updates U``: HBM bytes per
 launch of the kernel at its largest grid, from ``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``
 runs of ``bench.py --profile-sweeps``.  Each counter is scaled by what it reads for the
@@ -59,6 +64,33 @@ def trace(path, match, split_us=None):
         print(f"| {k} | {'x'.join(map(str, g))} | {len(v)} | {sum(v) / 1e6:.1f} | "
               f"{sum(v) / len(v) / 1e3:.2f} | {statistics.median(v) / 1e3:.2f} | "
               f"{min(v) / 1e3:.2f} | {max(v) / 1e3:.2f} |")
+
+
+def timeline(path, window, bins=20):
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]),
+                         short(r["Kernel_Name"])))
+    rows.sort()
+    sel = [(s, e) for s, e, k in rows if window in k]
+    if not sel:
+        raise SystemExit(f"no launch of {window} in the trace")
+    w0, w1 = sel[0][0], sel[-1][1]
+    inwin = [(s, e, k) for s, e, k in rows if s >= w0 and e <= w1]
+    busy = sum(e - s for s, e, _ in inwin)
+    print(f"window {(w1 - w0) / 1e9:.3f} s from the first to the last {window} launch: "
+          f"{len(inwin)} launches, GPU busy {busy / (w1 - w0):.3f}\n")
+    print(f"| bin | {window} launches | their average us | busy fraction |")
+    print("|---|---|---|---|")
+    step = (w1 - w0) / bins
+    for i in range(bins):
+        a, z = w0 + i * step, w0 + (i + 1) * step
+        part = [(s, e, k) for s, e, k in inwin if a <= s < z]
+        mine = [e - s for s, e, k in part if window in k]
+        frac = sum(e - s for s, e, _ in part) / step
+        avg = sum(mine) / len(mine) / 1e3 if mine else 0.0
+        print(f"| {i} | {len(mine)} | {avg:.1f} | {frac:.2f} |")
 
 
 def _counters(path):
@@ -143,6 +175,10 @@ def main(argv=None):
     t.add_argument("csv")
     t.add_argument("--match", default="socfv")
     t.add_argument("--split-us", type=float, default=None)
+    tl = sub.add_parser("timeline")
+    tl.add_argument("csv")
+    tl.add_argument("--window", required=True)
+    tl.add_argument("--bins", type=int, default=20)
     p = sub.add_parser("pmc")
     p.add_argument("--fetch", required=True)
     p.add_argument("--write", required=True)
@@ -157,6 +193,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         trace(a.csv, a.match, a.split_us)
+    elif a.cmd == "timeline":
+        timeline(a.csv, a.window, a.bins)
     else:
         pmc(a.fetch, a.write, a.sq, a.kernel, a.cells, a.updates, a.source, a.min_us)
 

@@ -8,10 +8,11 @@ dt and from the same start, and is compared cell by cell:
   residual r0 = b - A s0 of the start): the solve returns s0 + delta after one cycle, compared
   with s0 + ``oracle.correction_iterate(r0)``.
 
-Launch forms, by box and the two-sweep switch: two sweeps per launch with two cells per lane
-(even nx) or one (odd nx); one sweep per launch with four cells per lane (nx a multiple of 4)
-or one cell per lane.  Boxes span several tiles in x, y and z with ragged tails; 401 updates
-end every two-sweep run with one single sweep.
+Launch forms, by box and the two-sweep switch: two sweeps per launch on rows of 64 lanes or
+of 32 lanes (two per wave), with two cells per lane (even nx) or one (odd nx); one sweep per
+launch with four cells per lane (nx a multiple of 4) or one cell per lane.  Boxes span several
+tiles in x, y and z with ragged tails; 401 updates end every two-sweep run with one single
+sweep.
 
 Tolerance 1e-5 absolute (|s| <= 1): an FP32 update rounds about ten operations (6e-8 each),
 and the iteration is non-expansive (every update coefficient is >= 0 at cfl <= 1), so 400
@@ -106,7 +107,7 @@ def test_fp32_sweeps_match_oracle_at_equal_count(sv, orc, case, mode):
     m = MODES[mode]
     dt, plain, corr = oracle_refs(orc, solid, u, m)
     pb = sv.Problem.create(solid, *u)
-    runs = run_forms(sv, pb, m, (1, 0))
+    runs = run_forms(sv, pb, m, (2, 3, 0))
     pore = solid == 0
     for (two, prec), (s, st) in runs.items():
         assert st.status == sv.NOT_CONVERGED and st.iterations == SWEEPS, (two, prec)
@@ -131,7 +132,7 @@ def test_fp32_sweeps_with_activity_field(sv, orc):
     dt, plain, corr = oracle_refs(orc, solid, u, m, kappa=kappa.astype(np.float64))
     pb = sv.Problem.create(solid, *u, kappa=kappa)
     pore = solid == 0
-    for (two, prec), (s, st) in run_forms(sv, pb, m, (1, 0)).items():
+    for (two, prec), (s, st) in run_forms(sv, pb, m, (2, 3, 0)).items():
         ref = plain if prec == "fp32_plain" else corr
         d = np.abs(s - ref)[pore].max()
         print(f"activity two={two} {prec}: max |ds| {d:.2e}")
