@@ -55,7 +55,10 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per cell update of the FP32 correction sweep:
 # s in 4 + s out 4 + three lower-face velocities 12 + flag byte 1 + frozen residual 4
 BYTES_FP32_DC = 25
-BYTES_FP64 = 41          # FP64 sweep: 8 + 8 + 24 + 1
+# FP64 sweep: s in 8 + s out 8 + three lower-face velocities 24 + flag byte 1
+BYTES_FP64_SWEEP = 41
+# FP64 refresh: s64 in 8 + correction in 4 + faces 24 + flags 1 + s64 out 8 + residual out 4
+BYTES_REFRESH = 49
 STEP_SWEEPS = 400
 DOMINANT = "k_sweep2"
 
@@ -600,9 +603,25 @@ def main():
         pp = sv.params(precision="fp32", tol=0.0, max_iter=args.profile_sweeps, check_every=200)
         _, st = sv.solve_soc_steady(pb.ctx, pp, want_state=False)
         avg = st.ms_fp32 / max(st.it_fp32, 1)
+        # the FP64 plane-march kernels: 100 FP64 sweeps (partials on the last), and 20 short
+        # FP32 solves, each of which starts with a refresh and ends with the outputs
+        _, s64 = sv.solve_soc_steady(pb.ctx, sv.params(precision="fp64", tol=0.0, max_iter=100,
+                                                        check_every=100), want_state=False)
+        ms_ref, n_ref = 0.0, 0
+        for _ in range(20):
+            _, sr = sv.solve_soc_steady(pb.ctx, sv.params(precision="fp32", tol=0.0, max_iter=4,
+                                                           check_every=4), want_state=False)
+            ms_ref += sr.ms_refresh
+            n_ref += sr.cycles
+        sw64 = s64.ms_fp64 / max(s64.iterations, 1)
+        ref = ms_ref / max(n_ref, 1)
         print(json.dumps({"profile_sweeps": st.it_fp32, "avg_sweep_ms": avg,
                           "avg_launch_us": 2e3 * avg,
                           "achieved_GBs": BYTES_FP32_DC * ncell / (avg / 1e3) / 1e9,
+                          "fp64_sweeps": s64.iterations, "fp64_sweep_ms": sw64,
+                          "fp64_sweep_GBs": BYTES_FP64_SWEEP * ncell / (sw64 / 1e3) / 1e9,
+                          "refreshes": n_ref, "refresh_ms": ref,
+                          "refresh_GBs": BYTES_REFRESH * ncell / (ref / 1e3) / 1e9,
                           "cells": ncell, "tiles": tiles}), flush=True)
         return
     if args.leg == "upsampling":

@@ -1331,7 +1331,8 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
   std::vector<hipStream_t> saved(n);
   for (int i = 0; i < n; ++i) { saved[i] = ctxs[i]->st; ctxs[i]->st = bs; }
   BatchProb *d_probs = nullptr;
-  int *d_tiles = nullptr, *d_work = nullptr, *d_nwork = nullptr, *h_work = nullptr;
+  int *d_tiles = nullptr, *d_work = nullptr, *d_nwork = nullptr, *d_grab = nullptr,
+      *h_work = nullptr;
   double *d_part = nullptr, *d_out = nullptr, *h_out = nullptr;
   SolveCtl *d_ctl = nullptr, *h_ctl = nullptr;
   hipGraph_t graph = nullptr;
@@ -1340,8 +1341,8 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     (void)hipStreamSynchronize(bs);
-    hfree(d_probs); hfree(d_tiles); hfree(d_work); hfree(d_nwork); hfree(d_part); hfree(d_out);
-    hfree(d_ctl);
+    hfree(d_probs); hfree(d_tiles); hfree(d_work); hfree(d_nwork); hfree(d_grab);
+    hfree(d_part); hfree(d_out); hfree(d_ctl);
     if (h_work) (void)hipHostFree(h_work);
     if (h_out) (void)hipHostFree(h_out);
     if (h_ctl) (void)hipHostFree(h_ctl);
@@ -1470,6 +1471,13 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
     // their counts at d_nwork[0] and d_nwork[1]
     HIPCHK(hipMalloc(&d_work, sizeof(int) * 2 * max_tiles));
     HIPCHK(hipMalloc(&d_nwork, sizeof(int) * 2));
+    // item counter of the two-sweep launches (zeroed once by a copy; each launch leaves it
+    // at zero)
+    HIPCHK(hipMalloc(&d_grab, sizeof(int) * 2));
+    {
+      static const int zero2[2] = {0, 0};
+      HIPCHK(hipMemcpy(d_grab, zero2, sizeof(int) * 2, hipMemcpyHostToDevice));
+    }
     HIPCHK(hipMalloc(&d_part, sizeof(double) * NV * max_tiles));
     HIPCHK(hipMalloc(&d_out, sizeof(double) * NV * n));
     HIPCHK(hipHostMalloc(&h_work, sizeof(int) * (2 * max_tiles + 2), hipHostMallocDefault));
@@ -1585,7 +1593,7 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
     for (int j = 0; j < K / 2; ++j) {
       const bool lastp = j == K / 2 - 1;
       if (n_two_tiles)
-        launch_batch_sweep2(d_probs, d_tiles, d_work, d_nwork, nb2, j & 1,
+        launch_batch_sweep2(d_probs, d_tiles, d_work, d_nwork, d_grab, nb2, j & 1,
                             lastp ? d_part : nullptr, bs);
       if (n_one_tiles) {
         launch_batch_sweep(d_probs, d_tiles, d_work + max_tiles, d_nwork + 1, nb, bty, 0, true,

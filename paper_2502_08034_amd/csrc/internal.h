@@ -124,9 +124,10 @@ void launch_batch_sweep(const BatchProb *probs, const int *tile_prob, const int 
                         const int *nwork, int nblocks, int ty, int parity, bool dc,
                         double *partial, hipStream_t st);
 // two sweeps per launch over the work list's (problem, tile) items; correction form, no
-// activity field
+// activity field.  grab: two device ints, zero before the first launch; each launch takes
+// items from grab[0] and leaves both at zero when it ends
 void launch_batch_sweep2(const BatchProb *probs, const int *tile_prob, const int *work,
-                         const int *nwork, int nblocks, int parity, double *partial,
+                         const int *nwork, int *grab, int nblocks, int parity, double *partial,
                          hipStream_t st);
 void launch_batch_reduce(const BatchProb *probs, int n, const double *partial, double *out,
                          hipStream_t st);

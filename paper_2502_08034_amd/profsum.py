@@ -12,7 +12,7 @@ its last (how a batched solve's launches shrink as problems finish, and whether 
 leaves the GPU idle between them).
 
 ``pmc --fetch CSV --write CSV [--sq CSV] --kernel NAME --cells N --updates U``: HBM bytes per
-launch of the kernel at its largest grid, from ``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``
+launch of the kernel at its largest grid (NAME with template arguments selects one instance), from ``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``
 runs of ``bench.py --profile-sweeps``.  Each counter is scaled by what it reads for the
 calibration copies that run launches first (four converting copies of 2^28 FP32 values to
 FP64: 1 GiB read and 2 GiB written each), which fixes the counters' unit on this device.
@@ -114,8 +114,15 @@ def _calibration(rows, counter):
     return sum(cal) / len(cal)
 
 
+def _is_kernel(name, kernel):
+    # a NAME with template arguments ("k_march64<2, 1, true, true>") picks that instance,
+    # a plain NAME every instance
+    s = short(name)
+    return s.endswith(kernel) if "<" in kernel else s.split("<")[0].endswith(kernel)
+
+
 def _kernel_rows(rows, kernel, min_us=None):
-    mine = [r for r in rows if short(r[0]).split("<")[0].endswith(kernel)]
+    mine = [r for r in rows if _is_kernel(r[0], kernel)]
     if min_us is not None:
         mine = [r for r in mine if r[3] >= min_us * 1e3]
     if not mine:
