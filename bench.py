@@ -537,7 +537,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--skip", default="", help="comma list of legs to leave out: steady, cpu, "
                     "accuracy, adjoint, batch")
-    ap.add_argument("--leg", default=None, choices=["flow", "logpile", "upsampling", "batch"],
+    ap.add_argument("--leg", default=None,
+                    choices=["flow", "logpile", "upsampling", "batch", "adjoint"],
                     help="run one separate leg and print its own JSON line")
     ap.add_argument("--flow-cfl", type=float, default=3.5)
     ap.add_argument("--flow-workload", default="fibre256")
@@ -577,6 +578,12 @@ def main():
     if args.leg == "batch":
         out = batch_c4(sv, torch, budget_end)
         out["metric"] = "batched solve of 48 uneven problems (seeds 100-147) to residual 1e-8"
+        print(json.dumps(out), flush=True)
+        return
+    if args.leg == "adjoint":
+        solid2, u2 = fibre256_problem(sv)
+        out = adjoint_c5(sv, torch, solid2, u2, budget_end)
+        out["metric"] = "adjoint / forward time on 256x128x128 with a lognormal activity field"
         print(json.dumps(out), flush=True)
         return
     if args.leg == "flow":

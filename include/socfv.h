@@ -181,8 +181,8 @@ int socfv_evaluate(socfv_ctx *c, const socfv_params *p, const double *s, socfv_s
  * values live in a static device array of 4 MiB per GPU (held until the process ends)
  * instead of the context's buffers, and it calls no hipMalloc / hipFree.  The context must
  * live on the current device (INVALID_ARG otherwise).  Limit: the grid's FP64 reduction
- * blocks, ceil(nx / 128) ceil(ny / 4) ceil(nz / zc) (64 for 128 when nx is odd; zc = 128, or
- * less on grids with under 2048 such blocks), times 8 partials plus 8 results must fit 2^19
+ * blocks, ceil(nx / 128) ceil(ny / 4) ceil(nz / zc) (64 for 128 when nx is odd; zc a power
+ * of two from 2 to 128 picked by the march's chunk rule), times 8 partials plus 8 results must fit 2^19
  * doubles: at most 65,535 blocks (a 1024 x 512 x 256 grid has 2,048; a grid 2 cells wide and
  * 262,144 deep has 65,536) (INVALID_ARG beyond).  The array is shared by every
  * call on that GPU and keeps the last call's contents (every value is written before it is

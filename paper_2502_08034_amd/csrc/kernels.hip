@@ -1535,17 +1535,31 @@ __global__ void __launch_bounds__(64 * M64_ROWS) k_march64(March64Args a, int gx
   if (RES || OP == M64_OUTPUTS) block_store<K>(acc, 0u, a.partial + (long long)K * blockIdx.x);
 }
 
-// z chunk of the march: at most 128 planes, fewer while the grid has under 2048 blocks.
-// Each chunk re-reads the plane below its first; on the 1024x512x256 slab chunks of 128
-// planes (2048 blocks) take 1.19 ms per FP64 sweep and 1.59 ms per refresh, against 1.36 and
-// 1.79 with chunks of 16 (16,384 blocks): a block's start (the plane below re-read, the first
-// plane's loads with nothing to overlap them) is paid once per chunk.
+// Blocks of the march resident at once on the chip: 256 CUs x 3 blocks of four waves (the
+// occupancy of the FP64 epilogues, three waves per SIMD).
+constexpr int M64_RESIDENT = 768;
+
+// z chunk of the march: the power of two from 128 planes down with the lowest
+// (rounds of resident blocks) x (planes a block marches + 8), the 8 standing for a block's
+// start (the plane below re-read, the first plane's loads with nothing to overlap them).
+// Measured per FP64 sweep, against halving the chunk while the grid had under 2048 blocks:
+// 1024x512x256 1.19 ms either way (128 planes), 256x128x128 39 us against 54, 175x89x89
+// 30 us against 48, 96x78x78 15 us against 19.5, 64x32x32 7.4 us either way (2 planes).
 static int march64_zc(const Grid &g) {
   const int W = (g.nx & 1) ? 1 : 2;
   const long long gxy = (long long)((g.nx + 64 * W - 1) / (64 * W)) * ((g.ny + M64_ROWS - 1) / M64_ROWS);
-  int zc = 128;
-  while (zc > 2 && gxy * ((g.nz + zc - 1) / zc) < 2048) zc /= 2;
-  return zc;
+  int best = 128;
+  long long best_cost = -1;
+  for (int zc = 128; zc >= 2; zc /= 2) {
+    const long long blocks = gxy * ((g.nz + zc - 1) / zc);
+    const long long cost =
+        (blocks + M64_RESIDENT - 1) / M64_RESIDENT * (std::min(zc, g.nz) + 8);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = zc;
+    }
+  }
+  return best;
 }
 
 static dim3 march64_grid(const Grid &g, int zc) {
