@@ -471,8 +471,8 @@ def stokes_flow(sv, torch, name="fibre256", cfl=0.5, tol=1e-9, max_steps=10**7, 
         ux, uy, uz, _, st = sv.solve_stokes(ctx, cfl=cfl, tol=tol, max_steps=max_steps)
     else:
         # large boxes: resumed calls of 2000 steps, each reporting its progress
-        ux, uy, uz, pr, st = sv.solve_stokes(ctx, cfl=cfl, tol=tol, max_steps=2000,
-                                             want_pressure=True)
+        ux, uy, uz, pr, st = sv.solve_stokes(ctx, cfl=cfl, tol=tol,
+                                             max_steps=min(2000, max_steps), want_pressure=True)
         steps, cg = st.steps, st.cg_iterations
         while st.status == sv.NOT_CONVERGED and steps < max_steps:
             log(f"flow {nx}x{ny}x{nz}: {steps} steps, change {st.change:.2e}, "
