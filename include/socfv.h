@@ -213,14 +213,15 @@ int socfv_solve_soc_adjoint(socfv_ctx *c, const socfv_params *p, double *dU_dkap
 /*
  * Many problems (contexts with geometry and velocity set; uneven sizes allowed) solved
  * together.  With every p[i].precision == SOCFV_FP32, each FP32 sweep is one launch over
- * a tile work list spanning all unfinished problems (persistent blocks, contiguous tile
- * runs per XCD), and each problem keeps its own dt, tau, FP64 refreshes and stopping rule
+ * a tile work list spanning all unfinished problems (persistent blocks taking tiles from a
+ * device counter), and each problem keeps its own dt, tau, FP64 refreshes and stopping rule
  * (its own p[i]), all decided on the device: one chunk of check_every sweeps (rounded up to
  * a multiple of 4) with the work lists, the per-problem residuals and decisions and the
  * refreshes is captured once as a hipGraph and replayed, the host reading the problems'
  * states every few chunks to re-tile the remaining ones; the single-sweep block shape is
- * chosen by timing candidates on the batch.  Other precisions solve the problems one after
- * another.  p, st: host arrays of n entries;
+ * chosen by timing candidates on the batch.  The FP64 polish of the converged problems runs
+ * as one launch per sweep over all of them (st[i].ms_fp64 is that shared time).  Other
+ * precisions solve the problems one after another.  p, st: host arrays of n entries;
  * s_out: host array of n device pointers (nullable, entries nullable).  Returns the worst
  * status (OK < NOT_CONVERGED) or the first error.
  */

@@ -1334,6 +1334,9 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
   int *d_tiles = nullptr, *d_work = nullptr, *d_nwork = nullptr, *d_grab = nullptr,
       *h_work = nullptr;
   double *d_part = nullptr, *d_out = nullptr, *h_out = nullptr;
+  BatchM64 *d_m = nullptr;               // batched FP64 polish: problem table, items, partials
+  int *d_mitem = nullptr;
+  double *d_mpart = nullptr;
   SolveCtl *d_ctl = nullptr, *h_ctl = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1342,7 +1345,7 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
     if (graph) (void)hipGraphDestroy(graph);
     (void)hipStreamSynchronize(bs);
     hfree(d_probs); hfree(d_tiles); hfree(d_work); hfree(d_nwork); hfree(d_grab);
-    hfree(d_part); hfree(d_out); hfree(d_ctl);
+    hfree(d_part); hfree(d_out); hfree(d_ctl); hfree(d_m); hfree(d_mitem); hfree(d_mpart);
     if (h_work) (void)hipHostFree(h_work);
     if (h_out) (void)hipHostFree(h_out);
     if (h_ctl) (void)hipHostFree(h_ctl);
@@ -1667,15 +1670,92 @@ int socfv_batch_solve(int n, socfv_ctx *const *ctxs, const socfv_params *p,
       res[i] = h.res;
       status[i] = h.state == CTL_DONE ? SOCFV_OK : SOCFV_NOT_CONVERGED;
     }
-    // FP64 polish, outputs and states per problem
+    // FP64 polish.  The first chunk of every converged problem's polish runs as batched FP64
+    // sweeps: one launch per sweep over all of them (one problem at a time, their small
+    // launches leave most of the chip idle and each costs a host launch).  Partials come from
+    // the launches where some problem ends its chunk; each problem's sums are overwritten up
+    // to its own last sweep.  A problem whose residual is still above tol after the chunk and
+    // whose polish budget is longer continues alone, as the one-problem solve does.
+    std::vector<long> npol(n, 0), nk(n, 0);
+    long kmax = 0, items_max = 0;
     for (int i = 0; i < n; ++i) {
-      socfv_ctx *c = ctxs[i];
       long np = p[i].polish_iters > 0 ? p[i].polish_iters : S[i].chunk_len();
       np += np & 1;
       np = std::min<long>(np, p[i].max_iter - S[i].it);
+      npol[i] = status[i] == SOCFV_OK && np > 0 ? np : 0;
+      nk[i] = std::min<long>(npol[i], S[i].chunk_len());
+      kmax = std::max(kmax, nk[i]);
+      if (nk[i]) items_max += march64_blocks(ctxs[i]->g);
+    }
+    if (kmax > 0) {
+      HIPCHK(hipMalloc(&d_m, sizeof(BatchM64) * n));
+      HIPCHK(hipMalloc(&d_mitem, sizeof(int) * items_max));
+      HIPCHK(hipMalloc(&d_mpart, sizeof(double) * NV * items_max));
+      std::vector<BatchM64> hm;
+      std::vector<int> hitem;
+      // the problems still polishing at sweep j
+      auto build_m = [&](long j) -> int {
+        hm.clear();
+        hitem.clear();
+        for (int i = 0; i < n; ++i) {
+          if (nk[i] <= j) continue;
+          socfv_ctx *c = ctxs[i];
+          BatchM64 b{};
+          b.a = S[i].sweep_args<double>(nullptr, nullptr, false, nullptr);
+          b.a.w = faces64(c);
+          b.pair[0] = c->s64[0];
+          b.pair[1] = c->s64[1];
+          b.c0 = cur[i];
+          march64_shape(c->g, b.gx, b.gy, b.gz, b.zc);
+          b.blk0 = (int)hitem.size();
+          b.prob = i;
+          const int nb = b.gx * b.gy * b.gz;
+          for (int t = 0; t < nb; ++t) hitem.push_back((int)hm.size());
+          hm.push_back(b);
+        }
+        HIPCHK(hipStreamSynchronize(bs));   // the previous tables' launches are done
+        HIPCHK(hipMemcpyAsync(d_m, hm.data(), sizeof(BatchM64) * hm.size(),
+                              hipMemcpyHostToDevice, bs));
+        HIPCHK(hipMemcpyAsync(d_mitem, hitem.data(), sizeof(int) * hitem.size(),
+                              hipMemcpyHostToDevice, bs));
+        HIPCHK(hipStreamSynchronize(bs));
+        return 0;
+      };
+      TRY(build_m(0));
+      std::vector<char> ends(kmax, 0);
+      for (int i = 0; i < n; ++i)
+        if (nk[i]) ends[nk[i] - 1] = 1;
+      HIPCHK(hipEventRecord(ctxs[0]->t0, bs));
+      for (long j = 0; j < kmax; ++j) {
+        if (j > 0 && ends[j - 1]) TRY(build_m(j));
+        launch_batch_march64(d_m, (int)hm.size(), d_mitem, (int)hitem.size(), (int)(j & 1),
+                             ends[j] ? d_mpart : nullptr, d_out, bs);
+      }
+      HIPCHK(hipEventRecord(ctxs[0]->t1, bs));
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(h_out, d_out, sizeof(double) * NV * n, hipMemcpyDeviceToHost, bs));
+      HIPCHK(hipStreamSynchronize(bs));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, ctxs[0]->t0, ctxs[0]->t1));
+      for (int i = 0; i < n; ++i) {
+        if (!nk[i]) continue;
+        const double *out = h_out + (size_t)NV * i;
+        S[i].it += nk[i];
+        S[i].it64 += nk[i];
+        S[i].sw64 += nk[i];
+        S[i].ms64 += ms;             // the batched polish, shared by every problem in it
+        cur[i] ^= (int)(nk[i] & 1);
+        res[i] = S[i].res_of(out[0]);
+        TRY(S[i].check(out, res[i]));
+      }
+    }
+    // outputs and states per problem
+    for (int i = 0; i < n; ++i) {
+      socfv_ctx *c = ctxs[i];
       double pres = res[i];
       int pc = cur[i];
-      if (status[i] == SOCFV_OK && np > 0) TRY(S[i].run_fp64(pc, pres, np));
+      if (nk[i] && pres >= p[i].tol && npol[i] > nk[i])
+        (void)S[i].run_fp64(pc, pres, npol[i] - nk[i]);
       cur[i] = pc;
       res[i] = pres;
       status[i] = pres < p[i].tol ? SOCFV_OK : SOCFV_NOT_CONVERGED;

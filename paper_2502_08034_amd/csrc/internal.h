@@ -259,7 +259,22 @@ void launch_adj_refresh(const AdjRefreshArgs &a, const Tiles &t, hipStream_t st)
 
 // FP64 sweeps (any nx) by the FP64 plane march; partials as for launch_sweep
 void launch_sweep64(const SweepArgs<double> &a, hipStream_t st);
-int march64_blocks(const Grid &g);   // blocks (partial slots) of any FP64 march launch
+int march64_blocks(const Grid &g);
+// Batched FP64 sweeps (the polish of a batched solve): one entry per problem of a launch
+struct BatchM64 {
+  SweepArgs<double> a;   // geometry, faces, flags, activity, dt, s_in, s_eq, Da, bounds
+  double *pair[2];       // the problem's two FP64 state buffers
+  int c0;                // buffer read at parity 0
+  int gx, gy, gz, zc;    // its march grid (march64_shape)
+  int blk0;              // its first item
+  int prob;              // its index in the batch (result slot)
+};
+void march64_shape(const Grid &g, int &gx, int &gy, int &gz, int &zc);
+// one FP64 sweep of every problem in probs[0..nprob) over nitems items; with partial (NV
+// doubles per item) also each problem's sums into out[NV prob]
+void launch_batch_march64(const BatchM64 *probs, int nprob, const int *item_prob, int nitems,
+                          int parity, double *partial, double *out, hipStream_t st);
+   // blocks (partial slots) of any FP64 march launch
 
 // outputs of a state: partial per block (NV2 = 8 slots):
 // [sum_out w s, sum_out w, F_in, F_in_adv, reaction, sum_R, sum R^2, -]

@@ -1387,20 +1387,13 @@ struct M64Acc {
 // partials as for the sweep (RES always).
 // OP = M64_OUTPUTS: partials [sum_out w s, sum_out w, F_in, F_in_adv, reaction, sum R,
 // sum R^2, -] of the state s (as the outputs entry points document).
+// One block of the march: block (bx, by, bz) of the grid, its partials (RES, OUTPUTS) to part.
 template <int W, int OP, bool RES, bool DELTA>
-__global__ void __launch_bounds__(64 * M64_ROWS) k_march64(March64Args a, int gx, int gy,
-                                                             int gz) {
+__device__ __forceinline__ void march64_block(const March64Args &a, int bx, int by, int bz,
+                                              double *part) {
   constexpr int K = M64Acc<OP>::K;
-  if (a.gate && *a.gate != a.gate_val) return;
-  if (a.sel) {
-    const int c = *a.sel;
-    a.s = a.pair[c];
-    a.s_new = a.pair[c ^ 1];
-  }
   const Grid g = a.g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const int L = xcd_tile(blockIdx.x, gx * gy * gz);
-  const int bx = L % gx, by = (L / gx) % gy, bz = L / (gx * gy);
   const int lane = threadIdx.x;
   const int x = bx * (64 * W) + W * lane;
   const int y = by * M64_ROWS + threadIdx.y;
@@ -1532,7 +1525,22 @@ __global__ void __launch_bounds__(64 * M64_ROWS) k_march64(March64Args a, int gx
     sc = sup;
     wzc = wzu;
   }
-  if (RES || OP == M64_OUTPUTS) block_store<K>(acc, 0u, a.partial + (long long)K * blockIdx.x);
+  if (RES || OP == M64_OUTPUTS) block_store<K>(acc, 0u, part);
+}
+
+template <int W, int OP, bool RES, bool DELTA>
+__global__ void __launch_bounds__(64 * M64_ROWS) k_march64(March64Args a, int gx, int gy,
+                                                             int gz) {
+  if (a.gate && *a.gate != a.gate_val) return;
+  if (a.sel) {
+    const int c = *a.sel;
+    a.s = a.pair[c];
+    a.s_new = a.pair[c ^ 1];
+  }
+  const int L = xcd_tile(blockIdx.x, gx * gy * gz);
+  march64_block<W, OP, RES, DELTA>(
+      a, L % gx, (L / gx) % gy, L / (gx * gy),
+      RES || OP == M64_OUTPUTS ? a.partial + (long long)M64Acc<OP>::K * blockIdx.x : nullptr);
 }
 
 // Blocks of the march resident at once on the chip: 256 CUs x 3 blocks of four waves (the
@@ -1590,6 +1598,79 @@ void launch_sweep64(const SweepArgs<double> &s, hipStream_t st) {
   a.pinned = s.pinned; a.lo = s.lo; a.hi = s.hi; a.partial = s.partial;
   if (s.partial) launch_march64<M64_SWEEP, true, false>(a, st);
   else launch_march64<M64_SWEEP, false, false>(a, st);
+}
+
+// Batched FP64 sweeps: one block per (problem, march block) item over every problem of the
+// table; item w belongs to problem item_prob[w] and is its block w - blk0.  Each problem's
+// buffers alternate with the launch parity (s = pair[c0 ^ parity]).  With RES the partials
+// [sum R^2, cells out of bounds, sum R, -] of item w go to partial[NV w].
+template <bool RES>
+__global__ void __launch_bounds__(64 * M64_ROWS) k_batch_march64(const BatchM64 *__restrict__ probs,
+                                                                 const int *__restrict__ item_prob,
+                                                                 int parity,
+                                                                 double *__restrict__ partial) {
+  const int w = blockIdx.x;
+  const BatchM64 &q = probs[item_prob[w]];
+  March64Args a{};
+  a.g = q.a.g;
+  a.flags = q.a.flags;
+  a.w = q.a.w;
+  a.kappa = q.a.kappa;
+  a.s = q.pair[q.c0 ^ parity];
+  a.s_new = q.pair[q.c0 ^ parity ^ 1];
+  a.dt = q.a.dt;
+  a.s_in = q.a.s_in;
+  a.s_eq = q.a.s_eq;
+  a.Da = q.a.Da;
+  a.pinned = q.a.pinned;
+  a.lo = q.a.lo;
+  a.hi = q.a.hi;
+  a.zc = q.zc;
+  const int L = w - q.blk0;
+  const int bx = L % q.gx, by = (L / q.gx) % q.gy, bz = L / (q.gx * q.gy);
+  double *part = RES ? partial + (long long)NV * w : nullptr;
+  if (q.a.g.nx & 1) march64_block<1, M64_SWEEP, RES, false>(a, bx, by, bz, part);
+  else march64_block<2, M64_SWEEP, RES, false>(a, bx, by, bz, part);
+}
+
+// out[NV p] = sums of problem p's item partials (items blk0 .. blk0 + nblk - 1), fixed order
+__global__ void __launch_bounds__(256) k_batch_march64_reduce(const BatchM64 *__restrict__ probs,
+                                                              const double *__restrict__ partial,
+                                                              double *__restrict__ out) {
+  __shared__ double sh[256];
+  const BatchM64 &q = probs[blockIdx.x];
+  const int nb = q.gx * q.gy * q.gz;
+  for (int k = 0; k < NV; ++k) {
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < nb; j += 256) acc += partial[(long long)NV * (q.blk0 + j) + k];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+      if (threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(long long)NV * q.prob + k] = sh[0];
+    __syncthreads();
+  }
+}
+
+void march64_shape(const Grid &g, int &gx, int &gy, int &gz, int &zc) {
+  zc = march64_zc(g);
+  const dim3 d = march64_grid(g, zc);
+  gx = (int)d.x;
+  gy = (int)d.y;
+  gz = (int)d.z;
+}
+
+void launch_batch_march64(const BatchM64 *probs, int nprob, const int *item_prob, int nitems,
+                          int parity, double *partial, double *out, hipStream_t st) {
+  const dim3 block(64, M64_ROWS, 1);
+  if (partial) {
+    k_batch_march64<true><<<nitems, block, 0, st>>>(probs, item_prob, parity, partial);
+    k_batch_march64_reduce<<<nprob, 256, 0, st>>>(probs, partial, out);
+  } else {
+    k_batch_march64<false><<<nitems, block, 0, st>>>(probs, item_prob, parity, nullptr);
+  }
 }
 
 void launch_refresh(const RefreshArgs &r, const Tiles &, hipStream_t st) {
