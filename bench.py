@@ -534,7 +534,7 @@ def main():
     ap.add_argument("--scale", default=None, help="override the slab box, e.g. 256x128x64")
     ap.add_argument("--peclet", default="0.2,1,5")
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=24.0)
     ap.add_argument("--skip", default="", help="comma list of legs to leave out: steady, cpu, "
                     "accuracy, adjoint, batch")
     ap.add_argument("--leg", default=None,
