@@ -30,7 +30,9 @@
  * on the face); outlet faces: upwind value s_P, G = 0 (no concentration gradient); faces
  * shared with a fibre voxel and the y / z walls carry no flux and must have w = 0.
  * n_f(P) = number of faces P shares with fibre voxels (its specific area a = n_f / h).
- * Iteration: s <- s + dt R(s), dt = cfl / max_P (sum_f max(w_f,0) + sum_f G_f + lam_P).
+ * Iteration: s <- s + dt R(s), dt = cfl / max_P (sum_f max(w_f,0) + sum_f G_f + lam_P)
+ * (the maximum is scanned once per operator: again after socfv_set_velocity,
+ * socfv_set_activity, or a solve with another Da or mode).
  * Residual: res = tau * sqrt(mean over pore cells of R_P^2) = (tau/dt)||s^{n+1}-s^n||_rms
  * with tau = nx*ny*nz / Q (nominal volume over inlet flow).
  *

@@ -81,6 +81,12 @@ struct socfv_ctx {
   long npore = 0, nreact = 0, ninlet = 0, noutlet = 0;
   bool have_velocity = false;
   double Q_in = 0, div_max = 0, u_max = 0;
+  // the operator's version (velocity and activity; each set_* call bumps it) and the largest
+  // diagonal last scanned for it at (Da, pinned), which fixes dt
+  long long op_version = 0;
+  long long md_version = -1;
+  double md_Da = 0, md_value = 0;
+  int md_pinned = -1;
   Tiles tiles{4, 8, 32, 1};
   bool tiles_fixed = false;
   int ncu = 1;                   // compute units of the device (for the tile choice)
@@ -251,13 +257,20 @@ struct Solver {
     t = c->tiles;
     nblk = sweep_blocks(c->g, t);
     TRY(ensure_state(c));
-    // time step: cfl over the largest diagonal of the updated cells
-    const int mb = flags_blocks(c->g);
-    TRY(ensure_partial(c, (long long)mb * NV2 + 64));
-    launch_maxdiag(c->g, c->flags, faces64(c), c->kappa, p->Da, pinned, c->partial, mb, c->st);
-    HIPCHK(hipGetLastError());
-    double md = 0;
-    TRY(reduce_to_host(c, mb, 1, 1u, &md));
+    // time step: cfl over the largest diagonal of the updated cells (scanned once per
+    // operator and (Da, pinned); repeated solves on one operator reuse it)
+    double md = c->md_value;
+    if (c->md_version != c->op_version || c->md_Da != p->Da || c->md_pinned != (int)pinned) {
+      const int mb = flags_blocks(c->g);
+      TRY(ensure_partial(c, (long long)mb * NV2 + 64));
+      launch_maxdiag(c->g, c->flags, faces64(c), c->kappa, p->Da, pinned, c->partial, mb, c->st);
+      HIPCHK(hipGetLastError());
+      TRY(reduce_to_host(c, mb, 1, 1u, &md));
+      c->md_version = c->op_version;
+      c->md_Da = p->Da;
+      c->md_pinned = (int)pinned;
+      c->md_value = md;
+    }
     if (!(md > 0)) return fail(SOCFV_BAD_VELOCITY, "no updated cell (max diagonal %g)", md);
     dt = p->cfl / md;
     tau = (double)c->g.n / c->Q_in;
@@ -746,6 +759,7 @@ int socfv_set_velocity(socfv_ctx *c, const double *ux, const double *uy, const d
   if (!c->w32[3]) HIPCHK(hipMalloc(&c->w32[3], sizeof(float) * plane));
   if (!c->w64[3]) HIPCHK(hipMalloc(&c->w64[3], sizeof(double) * plane));
   TRY(enter(c, hip_stream));
+  ++c->op_version;
   const int nb = velocity_blocks(c->g);
   TRY(ensure_partial(c, 4ll * nb + 64));
   launch_velocity(c->g, c->flags, ux, uy, uz, q, c->w32, c->w64, c->partial, nb, c->st);
@@ -770,6 +784,7 @@ int socfv_set_velocity(socfv_ctx *c, const double *ux, const double *uy, const d
 int socfv_set_activity(socfv_ctx *c, const float *kappa, void *hip_stream) {
   if (!c) return fail(SOCFV_INVALID_ARG, "NULL context");
   c->have_state = false;
+  ++c->op_version;
   if (!kappa) {
     if (c->kappa) hfree(c->kappa);
     c->kappa = nullptr;

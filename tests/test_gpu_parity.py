@@ -190,6 +190,40 @@ def test_activity_field(sv, orc):
     assert np.abs(s.cpu().numpy() - sx)[solid == 0].max() < 1e-8
 
 
+def test_time_step_follows_the_operator(sv, orc):
+    # dt = cfl / (largest diagonal of the updated cells); the library scans the diagonal once
+    # per operator and (Da, mode), so every change of Da, mode, flow rate or activity field
+    # must give the oracle's dt again
+    solid, u = CASES["ragged70x37x29"]()
+    kappa = I.lognormal_activity(solid, 0.3, seed=5)
+    pb = make(sv, solid, u)
+
+    def dt_of(**kw):
+        p = sv.params(precision="fp32", tol=0.0, max_iter=4, check_every=4, **kw)
+        return sv.solve_soc_steady(pb.ctx, p, want_state=False)[1].dt
+
+    def oracle_dt(q=1.0, Da=0.45, pinned=False, kap=None):
+        op = orc.Problem(solid, *(a * q for a in u), s_in=1.0, s_eq=0.0, Da=Da, pinned=pinned,
+                         kappa=None if kap is None else kap.astype(np.float64))
+        return 0.4 / orc.max_diag(op)
+
+    steps = [
+        (dict(), dict()),
+        (dict(), dict()),                                    # the same operator again
+        (dict(Da=2.0), dict(Da=2.0)),
+        (dict(mode=1, s_in=0.0, s_eq=1.0, Da=0.0), dict(Da=0.0, pinned=True)),
+        (dict(), dict()),
+    ]
+    for kw, okw in steps:
+        assert dt_of(**kw) == pytest.approx(oracle_dt(**okw), rel=1e-13), kw
+    pb.set_flow_rate(3.0)
+    assert dt_of() == pytest.approx(oracle_dt(q=3.0), rel=1e-13)
+    pb.set_activity(cuda(kappa, torch.float32))
+    assert dt_of() == pytest.approx(oracle_dt(q=3.0, kap=kappa), rel=1e-13)
+    pb.set_activity(None)
+    assert dt_of() == pytest.approx(oracle_dt(q=3.0), rel=1e-13)
+
+
 def test_warm_start_resume(sv):
     solid, u = CASES["fibre64"]()
     pb = make(sv, solid, u)
