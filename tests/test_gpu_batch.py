@@ -82,6 +82,26 @@ def test_batch_exact_on_small_cases(sv, orc):
         assert abs(st.U - Ux) <= 1e-6 * Ux
 
 
+def test_batch_polish_lengths_differ(sv, orc):
+    # the batched FP64 polish runs each converged problem's first polish chunk (polish_iters,
+    # else check_every) in shared launches; problems whose chunk ends earlier leave the
+    # launches' table, which is rebuilt for the rest
+    probs = small_batch(4, 800)
+    lengths = [dict(check_every=100), dict(check_every=200, polish_iters=50),
+               dict(check_every=300), dict(check_every=100, polish_iters=150)]
+    params = [sv.params(precision="fp32", tol=1e-9, **kw) for kw in lengths]
+    expect = [100, 50, 300, 100]   # a polish longer than check_every stops after its first
+                                   # chunk once the residual is below tol, as alone
+    _, states, stats = run_batch(sv, probs, params)
+    for k, (p, s, st) in enumerate(zip(probs, states, stats)):
+        assert st.status == sv.OK, (k, st.status)
+        assert st.sweeps_fp64 == expect[k], (k, st.sweeps_fp64)
+        op = orc.Problem(p["solid"], *p["velocity"], s_in=1.0, s_eq=0.0, Da=0.45)
+        assert orc.residual_norm(op, s.cpu().numpy()) < 1.5e-9
+        o = orc.outputs(op, s.cpu().numpy())
+        assert abs(o["U"] - st.U) <= 1e-12 * max(1.0, abs(st.U))
+
+
 def test_batch48_design_sweep(sv, orc):
     """48 geometries from 64^3 to 192 x 96 x 96, porosity 0.70-0.90, radius 3-6, Peclet
     0.1-10, each to its own residual 1e-8 in one batched solve."""
