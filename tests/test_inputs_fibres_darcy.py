@@ -1,6 +1,7 @@
-"""The Darcy stand-in velocity that every workload uses (CPU): staggered layout, no flux
+"""The synthetic inputs every workload uses (CPU).  Darcy stand-in velocity: staggered layout, no flux
 through closed faces, discrete divergence-free pore cells, inflow equal to outflow, and
-linearity in the Peclet scale."""
+linearity in the Peclet scale.  Fibre boxes: porosity near its target, every pore cell reachable
+from the inlet."""
 import numpy as np
 import pytest
 
@@ -45,3 +46,35 @@ def test_linear_in_the_peclet_scale(box):
     u3 = I.darcy_velocity(solid, 3.0)
     for a, b in zip(u1, u3):
         assert np.allclose(b, 3.0 * a, rtol=1e-9, atol=1e-12 * np.abs(b).max())
+
+
+def reachable_from_inlet(pore):
+    # flood fill through shared faces by repeated dilation (independent of the generator's
+    # labelling): the pore cells a fluid parcel entering at x = 0 can reach
+    r = np.zeros_like(pore)
+    r[:, :, 0] = pore[:, :, 0]
+    while True:
+        g = r.copy()
+        g[:, :, 1:] |= r[:, :, :-1]
+        g[:, :, :-1] |= r[:, :, 1:]
+        g[:, 1:, :] |= r[:, :-1, :]
+        g[:, :-1, :] |= r[:, 1:, :]
+        g[1:] |= r[:-1]
+        g[:-1] |= r[1:]
+        g &= pore
+        if np.array_equal(g, r):
+            return r
+        r = g
+
+
+@pytest.mark.parametrize("kind", ["nonoverlap", "boolean"])
+def test_fibre_boxes_reach_their_porosity_and_the_inlet(kind):
+    if kind == "nonoverlap":
+        geo = I.fibres_nonoverlap(64, 32, 32, 3.0, 0.85, 11)
+    else:
+        geo = I.fibres_boolean(64, 32, 32, 3.0, 0.80, 12)
+    pore = geo.solid == 0
+    assert geo.porosity == pytest.approx(pore.mean(), abs=1e-12)
+    assert abs(geo.porosity - (0.85 if kind == "nonoverlap" else 0.80)) < 0.03
+    assert np.array_equal(reachable_from_inlet(pore), pore)
+    assert pore[:, :, -1].any()                          # the flow can leave
