@@ -1,7 +1,9 @@
-"""The synthetic inputs every workload uses (CPU).  Darcy stand-in velocity: staggered layout, no flux
-through closed faces, discrete divergence-free pore cells, inflow equal to outflow, and
-linearity in the Peclet scale.  Fibre boxes: porosity near its target, every pore cell reachable
-from the inlet."""
+"""The synthetic inputs every workload uses (CPU).
+
+Darcy stand-in velocity: staggered layout, no flux through closed faces, discrete
+divergence-free pore cells, inflow equal to outflow, linearity in the Peclet scale.  Fibre
+boxes: porosity near its target, every pore cell reachable from the inlet.
+"""
 import numpy as np
 import pytest
 
